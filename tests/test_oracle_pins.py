@@ -1,0 +1,367 @@
+"""Pins for the CPU oracle: each checks it against something other than itself
+(a library routine, an independent algebraic route, a closed form, finite
+differences, or values printed in the paper), chosen so that a plausible slip
+in the oracle (dropped term, wrong sign, wrong index, transposed operand)
+fails at least one of them.  CPU only."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import torch
+
+import oracle as O
+import oracle.hodlr_oracle as OH
+import workloads as W
+from conftest import read_golden
+
+
+def _mk(n, leaf, rank, seed=0, offsets=None, shift=4.0):
+    inp = W.synthetic(n, leaf, rank, seed=seed, leaf_offsets=offsets, shift=shift)
+    return O.from_inputs(inp)
+
+
+def _nonuniform_offsets(n, L, seed):
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.5, 1.5, 1 << L)
+    sizes = np.maximum(8, np.round(w / w.sum() * n)).astype(np.int64)
+    sizes[-1] += n - sizes.sum()
+    return np.concatenate([[0], np.cumsum(sizes)])
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+CASES = [
+    dict(n=512, leaf=64, rank=8),                 # L=3 uniform
+    dict(n=1024, leaf=32, rank=[4, 6, 8, 2, 5]),  # L=5 per-level ranks
+    dict(n=600, leaf=None, rank=[5, 0, 7], L=3),  # non-uniform leaves, a rank-0 level
+    dict(n=256, leaf=256, rank=[]),               # L=0: one leaf
+]
+
+
+def _case(c, seed=0):
+    if c.get("leaf") is None:
+        off = _nonuniform_offsets(c["n"], c["L"], seed)
+        return _mk(c["n"], None, c["rank"], seed=seed, offsets=off)
+    return _mk(c["n"], c["leaf"], c["rank"], seed=seed)
+
+
+# ---- the paper's own fixtures ------------------------------------------------
+
+def test_tree_example_of_fig_tree():
+    rows = read_golden("tree_fig_example.txt")
+    n = int(rows[0].split()[1])
+    L = int(rows[1].split()[1])
+    H = O.Hodlr(W.uniform_offsets(n, L), [1] * L, np.zeros((n, n >> L)), np.zeros((n, L)), np.zeros((n, L)))
+    for line in rows[2:]:
+        h, first, last = map(int, line.split())
+        level = h.bit_length() - 1
+        s, e = O.node_range(H, level, h - (1 << level))
+        assert (s + 1, e) == (first, last), h
+
+
+def test_storage_theorem_against_table_memory():
+    """mN + 2 r N L entries (with the appendix rank profiles) reproduce the
+    tables' memory columns; complex rows carry extra K storage, hence 5 %."""
+    from paper_2208_06290_amd.model import storage_entries
+    for line in read_golden("appendix_ranks.txt"):
+        head, ranks = line.split(":")
+        name, n, L, field, nbytes, mem = head.split()
+        n, L, nbytes, mem = int(n), int(L), int(nbytes), float(mem)
+        ranks = [int(x) for x in ranks.split()]
+        assert len(ranks) == L
+        gb = storage_entries(W.uniform_offsets(n, L), ranks) * nbytes / 1e9
+        tol = 0.03 if field == "real" else 0.05
+        assert abs(gb - mem) / mem < tol, (name, gb, mem)
+
+
+def test_cost_formulas_reduce_to_closed_forms():
+    from paper_2208_06290_amd import model
+    for n, m, r in ((4096, 64, 16), (1 << 20, 256, 32), (1 << 22, 256, 64)):
+        L = int(np.log2(n // m))
+        off = W.uniform_offsets(n, L)
+        assert model.factor_flops_paper(off, [r] * L) == pytest.approx(
+            model.paper_closed_form_factor(n, m, r, L), rel=1e-12)
+        assert model.solve_flops(off, [r] * L) == pytest.approx(2 * m * n + 4 * r * n * L, rel=1e-12)
+        assert model.storage_entries(off, [r] * L) == m * n + 2 * r * n * L
+
+
+# ---- library-routine and independent-route pins ------------------------------
+
+@pytest.mark.parametrize("c", CASES)
+def test_recursion_matches_dense_lu(c):
+    H = _case(c)
+    A = O.assemble_dense(H)
+    B = np.random.default_rng(1).standard_normal((H.N, 3))
+    X = O.solve(O.factor(H), B)
+    Xd = sla.lu_solve(sla.lu_factor(A), B)
+    assert _rel(X, Xd) < 1e-12
+
+
+@pytest.mark.parametrize("c", CASES[:3])
+def test_recursion_matches_extended_sparse_system(c):
+    H = _case(c, seed=3)
+    b = np.random.default_rng(2).standard_normal(H.N)
+    x = O.solve(O.factor(H), b)
+    xs = O.extended_sparse_solve(H.offsets, H.ranks, H.D, H.U, H.V, b)
+    assert _rel(x, xs) < 1e-12
+
+
+def test_manufactured_solution():
+    H = _mk(2048, 64, 12, seed=5)
+    xt = np.random.default_rng(3).standard_normal(H.N)
+    b = O.assemble_dense(H) @ xt
+    x = O.solve(O.factor(H), b)
+    assert _rel(x, xt) < 1e-12
+
+
+def test_single_leaf_is_plain_lu():
+    H = _mk(200, 200, [], seed=2)
+    b = np.random.default_rng(0).standard_normal(200)
+    F = O.factor(H)
+    lu, piv = sla.lu_factor(H.D[:, :200])
+    assert np.array_equal(F["lu"][0], lu) and np.array_equal(F["lu"][1], piv)
+    assert np.array_equal(O.solve(F, b), sla.lu_solve((lu, piv), b))
+
+
+def test_zero_generators_give_block_diagonal_solve():
+    H = _mk(512, 64, 8, seed=4)
+    H.U[:] = 0.0
+    b = np.random.default_rng(0).standard_normal(512)
+    x = O.solve(O.factor(H), b)
+    for i in range(8):
+        s, e = 64 * i, 64 * (i + 1)
+        np.testing.assert_allclose(x[s:e], np.linalg.solve(H.D[s:e, :64], b[s:e]), rtol=1e-13, atol=1e-15)
+
+
+def test_one_level_is_the_two_by_two_woodbury_solution():
+    """L = 1: Theorem 'Correctness of recursion' says x = z - Y w solves the 2x2
+    block system; compare with a dense solve of that block system."""
+    H = _mk(128, 64, 10, seed=6)
+    A = O.assemble_dense(H)
+    b = np.random.default_rng(0).standard_normal(128)
+    assert _rel(O.solve(O.factor(H), b), np.linalg.solve(A, b)) < 1e-13
+
+
+def test_Y_blocks_equal_subtree_solves():
+    """After factorization every Y_a = A_a^{-1} U_a, with A_a the principal
+    submatrix of the assembled matrix on I_a."""
+    H = _mk(1024, 32, [6, 5, 4, 8, 3], seed=7)
+    A = O.assemble_dense(H)
+    Y = O.y_big(O.factor(H))
+    for level in range(1, H.L + 1):
+        c0, c1 = H.colrange(level)
+        for i in range(1 << level):
+            s, e = O.node_range(H, level, i)
+            ref = np.linalg.solve(A[s:e, s:e], H.U[s:e, c0:c1])
+            assert _rel(Y[s:e, c0:c1], ref) < 1e-12
+
+
+def test_factorization_reproduces_A():
+    """Section III-E: A = A^{(L+1)} A^{(L)} ... A^{(1)} with the block-diagonal
+    leaf factor first and, per level, 2x2 factors [[I, Y_a V_b^T], [Y_b V_a^T, I]]."""
+    H = _mk(512, 32, [5, 4, 6, 3], seed=8)
+    Y = O.y_big(O.factor(H))
+    N = H.N
+    P = np.zeros((N, N))
+    for i in range(1 << H.L):
+        s, e = O.node_range(H, H.L, i)
+        P[s:e, s:e] = H.D[s:e, :e - s]
+    for level in range(H.L, 0, -1):
+        F = np.eye(N)
+        c0, c1 = H.colrange(level)
+        for p in range(1 << (level - 1)):
+            sa, ea = O.node_range(H, level, 2 * p)
+            sb, eb = O.node_range(H, level, 2 * p + 1)
+            F[sa:ea, sb:eb] = Y[sa:ea, c0:c1] @ H.V[sb:eb, c0:c1].T
+            F[sb:eb, sa:ea] = Y[sb:eb, c0:c1] @ H.V[sa:ea, c0:c1].T
+        P = P @ F
+    A = O.assemble_dense(H)
+    assert _rel(P, A) < 1e-13
+
+
+def test_assembly_matches_the_uncompressed_operators():
+    """The assembled HODLR matrix of a generated BIE / kernel workload equals the
+    full operator up to compression error: a misplaced or transposed block
+    would show up as an O(1) error."""
+    n = 2048
+    inp = W.bie_star(n, 128, 32)
+    ent = W.hodlr_inputs._BieEntries(n, "cpu")
+    full = ent.diag_block(torch.arange(n)[None])[0].numpy()
+    assert _rel(O.assemble_dense(O.from_inputs(inp)), full) < 1e-7
+    inp = W.kernel_matrix(1024, 64, 32, "gauss", 2, 1e-2, seed=1)
+    H = O.from_inputs(inp)
+    rng = np.random.default_rng(1 * 7919 + 17)
+    pts = rng.random((1024, 2))
+    pts = pts[W.rcb_order(pts, 64)]
+    d2 = ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1)
+    K = np.exp(-d2 / (2 * 0.05 ** 2)) + 1e-2 * np.eye(1024)
+    assert _rel(O.assemble_dense(H), K) < 1e-3
+
+
+# ---- adjoint and gradients --------------------------------------------------------
+
+def test_adjoint_dot_test_and_dense():
+    H = _case(CASES[1], seed=9)
+    A = O.assemble_dense(H)
+    rng = np.random.default_rng(4)
+    b, c = rng.standard_normal(H.N), rng.standard_normal(H.N)
+    x = O.solve(O.factor(H), b)
+    lam = O.solve_adjoint(H, c)
+    assert abs(x @ c - b @ lam) < 1e-12 * abs(x @ c) + 1e-13
+    assert _rel(lam, np.linalg.solve(A.T, c)) < 1e-12
+
+
+def test_adjoint_of_symmetric_matrix_is_forward_solve():
+    H = _mk(512, 64, 8, seed=10)
+    H.V[:] = H.U
+    for i in range(8):
+        s = 64 * i
+        blk = H.D[s:s + 64, :64]
+        H.D[s:s + 64, :64] = 0.5 * (blk + blk.T)
+    b = np.random.default_rng(5).standard_normal(512)
+    assert _rel(O.solve_adjoint(H, b), O.solve(O.factor(H), b)) < 1e-13
+
+
+def test_matvec_transpose_consistency():
+    H = _case(CASES[2], seed=11)
+    A = O.assemble_dense(H)
+    X = np.random.default_rng(6).standard_normal((H.N, 2))
+    assert _rel(O.matvec(H, X), A @ X) < 1e-14
+    assert _rel(O.matvec(H, X, trans=True), A.T @ X) < 1e-14
+
+
+def test_gradients_against_central_differences():
+    H = _mk(256, 32, [4, 3, 5], seed=12)
+    rng = np.random.default_rng(7)
+    b = rng.standard_normal(H.N)
+    t = rng.standard_normal(H.N)
+    L0, x, lam, dD, dU, dV = O.loss_and_grads(H, b, t)
+
+    def loss(Hp, bp):
+        A = O.assemble_dense(Hp)
+        return float(np.sum((np.linalg.solve(A, bp) - t) ** 2))
+
+    h = 1e-4
+    picks = []
+    for _ in range(6):
+        picks.append(("b", rng.integers(H.N), 0))
+        i = rng.integers(H.N)
+        leaf = i // 32
+        picks.append(("D", i, rng.integers(32)))
+        picks.append(("U", rng.integers(H.N), rng.integers(12)))
+        picks.append(("V", rng.integers(H.N), rng.integers(12)))
+    for kind, i, j in picks:
+        def perturbed(delta):
+            Hp = O.Hodlr(H.offsets, H.ranks, H.D.copy(), H.U.copy(), H.V.copy())
+            bp = b.copy()
+            if kind == "b":
+                bp[i] += delta
+            else:
+                getattr(Hp, kind)[i, j] += delta
+            return loss(Hp, bp)
+        fd = (perturbed(h) - perturbed(-h)) / (2 * h)
+        g = lam[i] if kind == "b" else {"D": dD, "U": dU, "V": dV}[kind][i, j]
+        assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (kind, i, j, fd, g)
+
+
+def test_dense_gradient_restricted_to_structure():
+    """-lambda x^T of the dense problem, pulled back through A(I_a,I_b) = U_a V_b^T
+    by the chain rule written independently with dense blocks."""
+    H = _mk(256, 64, [5, 6], seed=13)
+    A = O.assemble_dense(H)
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal(256)
+    t = rng.standard_normal(256)
+    x = np.linalg.solve(A, b)
+    lam = np.linalg.solve(A.T, 2 * (x - t))
+    G = -np.outer(lam, x)                     # dL/dA
+    _, _, lam_o, dD, dU, dV = O.loss_and_grads(H, b, t)
+    assert _rel(lam_o, lam) < 1e-12
+    for i in range(4):
+        s = 64 * i
+        assert _rel(dD[s:s + 64, :64], G[s:s + 64, s:s + 64]) < 1e-12
+    for level in (1, 2):
+        c0, c1 = H.colrange(level)
+        for a in range(1 << level):
+            sa, ea = O.node_range(H, level, a)
+            sb, eb = O.node_range(H, level, a ^ 1)
+            Gab = G[sa:ea, sb:eb]
+            assert _rel(dU[sa:ea, c0:c1], Gab @ H.V[sb:eb, c0:c1]) < 1e-12
+            assert _rel(dV[sb:eb, c0:c1], Gab.T @ H.U[sa:ea, c0:c1]) < 1e-12
+
+
+# ---- refinement ---------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec,max_it", [("fp32", 4), ("bf16", 12)])
+def test_refinement_reaches_1e10(prec, max_it):
+    H = _mk(2048, 64, 16, seed=14)
+    b = np.random.default_rng(9).standard_normal(H.N)
+    x, it, res, ok = O.refine(H, O.low_precision_solver(H, prec), b, tol=1e-10)
+    assert ok and it <= max_it
+    assert O.relres(H, x, b) <= 1e-10
+    xd = np.linalg.solve(O.assemble_dense(H), b)
+    assert _rel(x, xd) < 1e-9
+
+
+def test_refinement_reports_non_convergence():
+    """An ill-conditioned matrix (kappa * u_bf16 >> 1) must not report success."""
+    H = _mk(256, 32, 4, seed=15, shift=0.0)
+    H.D[:, :] *= 1e-4
+    b = np.random.default_rng(10).standard_normal(H.N)
+    x, it, res, ok = O.refine(H, O.low_precision_solver(H, "bf16"), b, tol=1e-10, max_iter=8)
+    assert not ok
+
+
+# ---- singular inputs ------------------------------------------------------------------
+
+def test_singular_leaf_is_reported():
+    H = _mk(128, 32, 4, seed=16)
+    H.D[32:64, 5] = 0.0        # leaf 1 gets a zero column
+    with pytest.raises(np.linalg.LinAlgError):
+        O.factor(H)
+
+
+def test_singular_coupling_matrix_is_reported():
+    """D = I and U_a = V_b = U_b = V_a = e_1 give K = [[1, 1], [1, 1]]."""
+    off = np.array([0, 1, 2])
+    e = np.ones((2, 1))
+    H = O.Hodlr(off, [1], np.ones((2, 1)), e.copy(), e.copy())
+    with pytest.raises(np.linalg.LinAlgError):
+        O.factor(H)
+
+
+# ---- planted mistakes: the pins above must catch them -----------------------------------
+
+def _planted(monkeypatch, name, fn):
+    monkeypatch.setattr(OH, name, fn)
+    H = _case(CASES[1], seed=17)
+    A = O.assemble_dense(H)
+    b = np.random.default_rng(0).standard_normal(H.N)
+    return _rel(O.solve(O.factor(H), b), np.linalg.solve(A, b))
+
+
+@pytest.mark.parametrize("mistake", ["sign", "swapV", "transT", "dropI"])
+def test_planted_mistakes_break_dense_parity(monkeypatch, mistake):
+    good_k, good_c = OH._coupling_matrix, OH._combine
+    if mistake == "sign":
+        err = _planted(monkeypatch, "_combine",
+                       lambda Za, Zb, Ya, Yb, W: good_c(Za, Zb, -Ya, -Yb, W))
+    elif mistake == "swapV":
+        err = _planted(monkeypatch, "_coupling_matrix",
+                       lambda Va, Ya, Vb, Yb: good_k(Vb, Ya, Va, Yb) if Va.shape == Vb.shape else good_k(Va, Ya, Vb, Yb))
+    elif mistake == "transT":
+        def k(Va, Ya, Vb, Yb):
+            K = good_k(Va, Ya, Vb, Yb)
+            r = Ya.shape[1]
+            K[:r, :r] = K[:r, :r].T.copy()
+            return K
+        err = _planted(monkeypatch, "_coupling_matrix", k)
+    else:
+        def k(Va, Ya, Vb, Yb):
+            K = good_k(Va, Ya, Vb, Yb)
+            r = Ya.shape[1]
+            K[:r, r:] = 0.0
+            return K
+        err = _planted(monkeypatch, "_coupling_matrix", k)
+    assert err > 1e-6
