@@ -1,0 +1,196 @@
+/*
+ * hodlr.h — C ABI of the MI355X (gfx950) HODLR factor/solve library.
+ *
+ * Problem (paper: Section I, the linear system A x = b; Section III, eq.
+ * "e:hxb"): A is an N x N HODLR matrix on a binary cluster tree T_L
+ * (Definition "Cluster tree"): level l has 2^l nodes, each a consecutive
+ * index set, siblings partition their parent.  A is given by
+ *   - its 2^L leaf diagonal blocks D_a = A(I_a, I_a), and
+ *   - low-rank generators for every sibling pair (a, b):
+ *       A(I_a, I_b) = U_a V_b^T            (eq. "e:rank", real field).
+ * The generators of all levels are concatenated into U_big / V_big
+ * (Fig. "f:cat", eq. "e:u"): level l (1 <= l <= L, rank r_l) occupies
+ * columns [R_{l-1}, R_l) with R_l = r_1 + ... + r_l, and node a's block is
+ * rows I_a of those columns.  The leaf blocks are stacked into
+ * D_big (Fig. "f:dk"): row block I_a, columns [0, |I_a|).
+ *
+ * Memory layout: every matrix argument is COLUMN-MAJOR with an explicit
+ * leading dimension (element (i, j) at ptr[i + j*ld]).  Device pointers
+ * unless marked "host".  Arguments are never freed by the library.
+ *
+ * Streams: every call is ordered on `stream` (a hipStream_t; NULL = the
+ * null stream).  Calls that return a convergence or singularity verdict
+ * synchronise `stream` once per verdict; all others are asynchronous.
+ *
+ * Errors: negative status = invalid argument / resource error, detected
+ * before any kernel is launched where possible; nothing is written then.
+ * Positive status = numerical verdict (see each call).
+ */
+#ifndef HODLR_H
+#define HODLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HODLR_F64 = 0,   /* IEEE double                                      */
+  HODLR_F32 = 1,   /* IEEE single                                      */
+  HODLR_BF16 = 2   /* bfloat16 MFMA operands, FP32 storage/accumulate  */
+} hodlr_dtype;
+
+typedef enum {
+  HODLR_OK = 0,
+  HODLR_ERR_ARG = -1,          /* bad shape, pointer, rank or leading dimension */
+  HODLR_ERR_ALLOC = -2,        /* device allocation failed                     */
+  HODLR_ERR_HIP = -3,          /* a HIP runtime call failed                    */
+  HODLR_ERR_UNSUPPORTED = -4,  /* valid but outside this build's limits        */
+  HODLR_ERR_SINGULAR = 1,      /* an exactly zero pivot in a leaf or a K       */
+  HODLR_ERR_NOT_CONVERGED = 2  /* iterative refinement did not reach tol       */
+} hodlr_status;
+
+/* Limits of this build. */
+#define HODLR_MAX_LEAF 256     /* largest leaf block |I_a|                      */
+#define HODLR_MAX_RANK 64      /* largest per-level rank r_l                    */
+#define HODLR_MAX_LEVELS 24
+
+/* A HODLR matrix (inputs of the factorization; Alg. "a:gpuf" "Require").
+ *   n             N >= 1
+ *   levels        L >= 0; the tree has 2^L leaves
+ *   leaf_offsets  host, 2^L + 1 strictly increasing int64, [0] = 0, [2^L] = N;
+ *                 node i of level l spans leaves [i 2^{L-l}, (i+1) 2^{L-l}).
+ *                 NULL = uniform tree (requires 2^L | N).
+ *   ranks         host, L entries, ranks[l-1] = r_l, 0 <= r_l <= HODLR_MAX_RANK
+ *                 and r_l <= size of every level-l node.  May be NULL if L = 0.
+ *   dtype         storage type of D, U, V: HODLR_F64 or HODLR_F32
+ *   D, ldd        N x m_max (m_max = largest leaf), ldd >= N
+ *   U, ldu        N x R (R = R_L), ldu >= N (ignored if R = 0)
+ *   V, ldv        N x R, ldv >= N
+ * The library only reads D, U, V.  A factorization keeps referring to them
+ * (refinement residuals and gradients), so they must outlive it unchanged. */
+typedef struct {
+  int64_t n;
+  int32_t levels;
+  const int64_t *leaf_offsets;
+  const int32_t *ranks;
+  hodlr_dtype dtype;
+  const void *D;
+  int64_t ldd;
+  const void *U;
+  int64_t ldu;
+  const void *V;
+  int64_t ldv;
+} hodlr_matrix;
+
+/* Opaque factorization (Alg. "a:gpuf" "Ensure": Y_big, the block LU
+ * factorizations of D_big^L and of K_big^0 .. K_big^{L-1}).  Owns its
+ * device memory; immutable after hodlr_factor except by hodlr_refactor. */
+typedef struct hodlr_factors hodlr_factors;
+
+/* First exactly-zero pivot, in factorization order (leaves first, then the
+ * coupling matrices from level L-1 up to 0).  level = L for a leaf (node =
+ * leaf index), else the parent level of the K; column is 0-based. */
+typedef struct {
+  int32_t level;
+  int32_t column;
+  int64_t node;
+} hodlr_info;
+
+/* Solve options.  refine = 0: one application of the stored factors in the
+ * factorization's precision.  refine = 1: FP64 iterative refinement around
+ * the factors, with an FP64 residual b - A x evaluated from the original
+ * D, U, V; stops when max over columns ||b - A x||_2 / ||b||_2 <= tol, fails
+ * with HODLR_ERR_NOT_CONVERGED after max_iter steps or when the residual
+ * grows on two consecutive steps. */
+typedef struct {
+  int32_t refine;
+  int32_t max_iter;
+  double tol;
+} hodlr_solve_opts;
+
+typedef struct {
+  int32_t iters;      /* refinement steps taken (0 without refinement)       */
+  int32_t converged;  /* 1 if relres <= tol                                   */
+  double relres;      /* final max-column relative residual (refine only)    */
+} hodlr_solve_stats;
+
+/* Factorization (Section III-B Alg. "a:fact" / Section III-C Alg. "a:gpuf"):
+ * batched LU with partial pivoting of every leaf, Y_big = D^{-1} U_big on all
+ * columns, then for l = L-1 .. 0: the coupling products V^T Y, the LU of
+ * K_g = [[V_a^T Y_a, I], [I, V_b^T Y_b]] (eq. "e:k") and the update of
+ * Y_big(:, 1:R_l) (eqs. "e:node1", "e:node2").
+ *   A        the matrix (see hodlr_matrix)
+ *   compute  HODLR_F64 (requires dtype F64), HODLR_F32 or HODLR_BF16
+ *   F        out: new factorization object (NULL on negative status)
+ * Returns HODLR_ERR_SINGULAR (factors kept but unusable; *info filled if
+ * info != NULL) when a pivot is exactly zero.  Synchronises the stream once
+ * (singularity verdict).  Allocates device memory (hipMalloc). */
+hodlr_status hodlr_factor(const hodlr_matrix *A, hodlr_dtype compute, void *stream,
+                          hodlr_factors **F, hodlr_info *info);
+
+/* Recompute the factorization in F's storage for new values of D, U, V
+ * with exactly the same tree, ranks, storage type and leading dimensions
+ * (pointers may change).  Allocates nothing.  Same verdicts as hodlr_factor. */
+hodlr_status hodlr_refactor(hodlr_factors *F, const hodlr_matrix *A, void *stream, hodlr_info *info);
+
+/* Solution (Alg. "a:solve" / Alg. "a:gpus"): B <- A^{-1} B in place
+ * (x overwrites b).  B is N x nrhs FP64, ldb >= N, nrhs >= 0.  With
+ * opts == NULL or refine == 0 the solve runs in the factors' precision.
+ * st may be NULL. */
+hodlr_status hodlr_solve(const hodlr_factors *F, int64_t nrhs, double *B, int64_t ldb,
+                         const hodlr_solve_opts *opts, void *stream, hodlr_solve_stats *st);
+
+/* Adjoint solution B <- A^{-T} B on the same factors.  Uses the product
+ * form of Section III-E (A = D F_L ... F_1, each F a 2x2 block factor that
+ * eq. "e:wood" inverts): A^{-T} = D^{-T} F_L^{-T} ... F_1^{-T}, applied top
+ * level first with transposed coupling solves, leaf solves last.
+ * Refinement (opts->refine) uses the FP64 residual with A^T. */
+hodlr_status hodlr_solve_adjoint(const hodlr_factors *F, int64_t nrhs, double *B, int64_t ldb,
+                                 const hodlr_solve_opts *opts, void *stream, hodlr_solve_stats *st);
+
+/* FP64 matrix product Y = A X (trans = 0) or Y = A^T X (trans = 1), reading
+ * D, U, V in their storage type: y_a = D_a x_a + sum over levels of
+ * U_a (V_b^T x_b) for the sibling b of each ancestor-or-self a (eq. "e:rank").
+ * X: N x nrhs (ldx >= N), Y: N x nrhs (ldy >= N); X and Y must not overlap.
+ * Allocates temporary device memory. */
+hodlr_status hodlr_matvec(const hodlr_matrix *A, int32_t trans, int64_t nrhs, const double *X,
+                          int64_t ldx, double *Y, int64_t ldy, void *stream);
+
+/* Gradients of a scalar loss through x = A^{-1} b, given the solution X and
+ * the adjoint Lambda = A^{-T} dL/dx (both N x nrhs FP64): dL/dA = -Lambda X^T
+ * restricted to the HODLR parameters,
+ *   dD_a = -Lambda_a X_a^T, dU_a = -Lambda_a (V_b^T X_b)^T, dV_b = -X_b (U_a^T Lambda_a)^T.
+ * dD, dU, dV are written in the storage type and layout of F's D, U, V
+ * (N x m_max with ldd, N x R with ldu / ldv); entries of dD outside the
+ * leaf blocks are left untouched. */
+hodlr_status hodlr_grad(const hodlr_factors *F, int64_t nrhs, const double *X, int64_t ldx,
+                        const double *Lambda, int64_t ldl, void *dD, void *dU, void *dV,
+                        void *stream);
+
+/* Copy Y_big (N x R; level-l columns at rows I_a hold Y_a = A_a^{-1} U_a,
+ * eq. "e:recursion") into Y as FP64 (ldy >= N). */
+hodlr_status hodlr_factors_y(const hodlr_factors *F, double *Y, int64_t ldy, void *stream);
+
+/* Device bytes owned by F. */
+size_t hodlr_factor_bytes(const hodlr_factors *F);
+
+/* Release F (waits for its pending work). NULL is ignored. */
+void hodlr_destroy(hodlr_factors *F);
+
+const char *hodlr_status_string(hodlr_status s);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around
+ * every kernel of the library.  enable = 1 starts recording (clears totals),
+ * 0 stops.  hodlr_kernel_times fills up to `cap` entries: names[i] (static
+ * strings), total milliseconds and launch counts; returns the number of
+ * kernels seen.  Synchronises the recorded streams. */
+void hodlr_timing_enable(int32_t enable);
+int32_t hodlr_kernel_times(const char **names, double *total_ms, int64_t *launches, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HODLR_H */

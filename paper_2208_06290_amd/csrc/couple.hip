@@ -1,0 +1,388 @@
+// Coupling systems (Section III-A eq. "e:k"; Alg. "a:gpuf" form K / factor K /
+// solve W; Alg. "a:gpus" solve w):
+//
+//   K_g = [[V_a^T Y_a, I], [I, V_b^T Y_b]]   for the children a, b of parent g
+//
+// The products V^T Y arrive as per-tile partial sums (level pass) or as
+// segment sums of them; they are summed here in fixed order.
+//
+// couple_factor: one workgroup per parent; K is formed and LU-factored with
+//   partial pivoting in LDS (largest magnitude, lowest row on ties), then the
+//   right-hand sides [V_a^T Y_big(I_a, 1:R_l); V_b^T Y_big(I_b, 1:R_l)] are
+//   solved column group by column group (eq. "e:node1") into W.
+// couple_solve: one wave per parent; w = K^{-1} [V_a^T x_a; V_b^T x_b]
+//   (eq. "e:node3") or the transposed solve used by the adjoint.
+// Lanes own rows of the right-hand side (2r <= 128 -> two rows per lane) and
+// the pivot value of each elimination step is broadcast with readlane.
+#include "internal.h"
+
+namespace hodlr {
+
+// ---------------------------------------------------------------------------
+// segment sums: out[s] = sum of tiles [desc[s].x, desc[s].x + desc[s].y)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void segment_reduce_kernel(const int2* __restrict__ desc, int64_t elems, const T* __restrict__ P,
+                                      T* __restrict__ out) {
+  const int sg = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= elems) return;
+  const int2 d = desc[sg];
+  T acc = T(0);
+  for (int t = 0; t < d.y; ++t) acc += P[(int64_t)(d.x + t) * elems + e];
+  out[(int64_t)sg * elems + e] = acc;
+}
+
+template <typename T>
+hipError_t launch_segment_reduce(hipStream_t s, int nsegs, const int2* d_desc, int64_t elems, const T* P, T* out) {
+  if (nsegs == 0 || elems == 0) return hipSuccess;
+  dim3 grid((unsigned)((elems + 255) / 256), (unsigned)nsegs);
+  hipLaunchKernelGGL(segment_reduce_kernel<T>, grid, dim3(256), 0, s, d_desc, elems, P, out);
+  return hipGetLastError();
+}
+template hipError_t launch_segment_reduce<double>(hipStream_t, int, const int2*, int64_t, const double*, double*);
+template hipError_t launch_segment_reduce<float>(hipStream_t, int, const int2*, int64_t, const float*, float*);
+
+// sum over the segments of `node`: element (i, c) of an r x ncols col-major block
+template <typename T>
+__device__ __forceinline__ T seg_sum(const T* __restrict__ segs, const int32_t* __restrict__ seg_start, int node,
+                                     int64_t elems, int64_t idx) {
+  const int s0 = seg_start[node], s1 = seg_start[node + 1];
+  T acc = T(0);
+  for (int sg = s0; sg < s1; ++sg) acc += segs[(int64_t)sg * elems + idx];
+  return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ T bcast(T v, int srclane);
+template <>
+__device__ __forceinline__ double bcast<double>(double v, int srclane) {
+  int2 u = __builtin_bit_cast(int2, v);
+  u.x = __builtin_amdgcn_readlane(u.x, srclane);
+  u.y = __builtin_amdgcn_readlane(u.y, srclane);
+  return __builtin_bit_cast(double, u);
+}
+template <>
+__device__ __forceinline__ float bcast<float>(float v, int srclane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), srclane));
+}
+
+// One wave solves K z = y for NC right-hand-side columns held as x[slot][c]
+// (row = slot * 64 + lane).  Kf: LU factor (col-major, ld n2) in LDS or global,
+// kud: reciprocal diagonal.  Rows >= n2 are ignored.
+template <typename T, int NC, int TRANS>
+__device__ __forceinline__ void wave_lu_solve(T (&x)[2][NC], const T* Kf, const T* kud, int n2, int lane) {
+  if (!TRANS) {
+    // L (unit lower) then U
+    for (int j = 0; j < n2; ++j) {
+      const int sj = j >> 6, lj = j & 63;
+      T xj[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) xj[c] = bcast(sj ? x[1][c] : x[0][c], lj);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int row = s * 64 + lane;
+        if (row > j && row < n2) {
+          const T f = Kf[row + j * n2];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) x[s][c] -= f * xj[c];
+        }
+      }
+    }
+    for (int j = n2 - 1; j >= 0; --j) {
+      const int sj = j >> 6, lj = j & 63;
+      const T dinv = kud[j];
+      T xj[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) xj[c] = bcast(sj ? x[1][c] : x[0][c], lj) * dinv;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int row = s * 64 + lane;
+        if (row == j) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) x[s][c] = xj[c];
+        } else if (row < j) {
+          const T f = Kf[row + j * n2];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) x[s][c] -= f * xj[c];
+        }
+      }
+    }
+  } else {
+    // U^T (lower, non-unit) then L^T (unit upper)
+    for (int j = 0; j < n2; ++j) {
+      const int sj = j >> 6, lj = j & 63;
+      const T dinv = kud[j];
+      T xj[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) xj[c] = bcast(sj ? x[1][c] : x[0][c], lj) * dinv;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int row = s * 64 + lane;
+        if (row == j) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) x[s][c] = xj[c];
+        } else if (row > j && row < n2) {
+          const T f = Kf[j + row * n2];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) x[s][c] -= f * xj[c];
+        }
+      }
+    }
+    for (int j = n2 - 1; j >= 0; --j) {
+      const int sj = j >> 6, lj = j & 63;
+      T xj[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) xj[c] = bcast(sj ? x[1][c] : x[0][c], lj);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int row = s * 64 + lane;
+        if (row < j) {
+          const T f = Kf[j + row * n2];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) x[s][c] -= f * xj[c];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// couple_factor
+// ---------------------------------------------------------------------------
+constexpr int kCfThreads = 256;
+constexpr int kCfCols = 8;  // right-hand-side columns per wave and step
+
+template <typename T>
+__global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int Rp, const T* __restrict__ segs,
+                                                                   const int32_t* __restrict__ seg_start,
+                                                                   T* __restrict__ Klu, int32_t* __restrict__ Kpiv,
+                                                                   int32_t* __restrict__ Kperm,
+                                                                   T* __restrict__ Kud, T* __restrict__ W,
+                                                                   unsigned long long* info, int level, int L) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* K = reinterpret_cast<T*>(smem_raw);  // n2 x n2, col-major
+  __shared__ T redv[kCfThreads / 64];
+  __shared__ int redi[kCfThreads / 64];
+  __shared__ int spiv[2 * HODLR_MAX_RANK];
+  __shared__ int sperm[2 * HODLR_MAX_RANK];
+  __shared__ T spivval;
+
+  const int g = blockIdx.x;
+  const int a = 2 * g, b = 2 * g + 1;
+  const int n2 = 2 * r;
+  const int ncin = Rp + r;  // columns of the children's products: [W rhs | T]
+  const int64_t elems = (int64_t)r * ncin;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+
+  for (int e = tid; e < n2 * n2; e += kCfThreads) {
+    const int i = e % n2, j = e / n2;
+    T v;
+    if (i < r && j < r)
+      v = seg_sum(segs, seg_start, a, elems, i + (int64_t)(Rp + j) * r);
+    else if (i >= r && j >= r)
+      v = seg_sum(segs, seg_start, b, elems, (i - r) + (int64_t)(Rp + j - r) * r);
+    else if (i < r)
+      v = (j - r == i) ? T(1) : T(0);
+    else
+      v = (i - r == j) ? T(1) : T(0);
+    K[i + j * n2] = v;
+  }
+  __syncthreads();
+  for (int j = 0; j < n2; ++j) {
+    T best = T(-1);
+    int bi = 0x7fffffff;
+    if (tid >= j && tid < n2) {
+      best = fabs(K[tid + j * n2]);
+      bi = tid;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      T ov = __shfl_xor(best, off, 64);
+      int oi = __shfl_xor(bi, off, 64);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      redv[wid] = best;
+      redi[wid] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      T bv = redv[0];
+      int bx = redi[0];
+      for (int w = 1; w < kCfThreads / 64; ++w)
+        if (redv[w] > bv || (redv[w] == bv && redi[w] < bx)) {
+          bv = redv[w];
+          bx = redi[w];
+        }
+      if (bx >= n2) bx = j;  // no comparable candidate (NaN column): keep the diagonal
+      spiv[j] = bx;
+      spivval = K[bx + j * n2];
+      if (spivval == T(0))
+        atomicMin(info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16) |
+                            (unsigned long long)j);
+    }
+    __syncthreads();
+    const int p = spiv[j];
+    const T pivot = spivval;
+    if (p != j)
+      for (int c = tid; c < n2; c += kCfThreads) {
+        T t0 = K[j + c * n2];
+        K[j + c * n2] = K[p + c * n2];
+        K[p + c * n2] = t0;
+      }
+    __syncthreads();
+    if (pivot != T(0)) {
+      const T rinv = T(1) / pivot;
+      const int rem = n2 - j - 1;
+      for (int i = j + 1 + tid; i < n2; i += kCfThreads) K[i + j * n2] *= rinv;
+      __syncthreads();
+      for (int e = tid; e < rem * rem; e += kCfThreads) {
+        const int i = j + 1 + e % rem, c = j + 1 + e / rem;
+        K[i + c * n2] -= K[i + j * n2] * K[j + c * n2];
+      }
+    }
+    __syncthreads();
+  }
+  // store the factors, the composed permutation and the reciprocal diagonal
+  T* Kg = Klu + (int64_t)g * n2 * n2;
+  for (int e = tid; e < n2 * n2; e += kCfThreads) Kg[e] = K[e];
+  if (tid == 0) {
+    for (int i = 0; i < n2; ++i) sperm[i] = i;
+    for (int j = 0; j < n2; ++j) {
+      int p = spiv[j];
+      int t0 = sperm[j];
+      sperm[j] = sperm[p];
+      sperm[p] = t0;
+    }
+  }
+  __syncthreads();
+  T* kud_s = K + n2 * n2;  // reciprocal diagonal kept in LDS for the W solve
+  for (int i = tid; i < n2; i += kCfThreads) {
+    Kpiv[(int64_t)g * n2 + i] = spiv[i];
+    Kperm[(int64_t)g * n2 + i] = sperm[i];
+    const T d = T(1) / K[i + i * n2];
+    Kud[(int64_t)g * n2 + i] = d;
+    kud_s[i] = d;
+  }
+  __syncthreads();
+  if (Rp == 0) return;
+  // W = K^{-1} [V_a^T Y(I_a, 0:Rp); V_b^T Y(I_b, 0:Rp)], column groups per wave
+  T* Wg = W + (int64_t)g * n2 * Rp;
+  const int ngroups = (Rp + kCfCols - 1) / kCfCols;
+  for (int grp = wid; grp < ngroups; grp += kCfThreads / 64) {
+    const int cbase = grp * kCfCols;
+    T x[2][kCfCols];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int row = s * 64 + lane;
+#pragma unroll
+      for (int c = 0; c < kCfCols; ++c) {
+        T v = T(0);
+        if (row < n2 && cbase + c < Rp) {
+          const int src = sperm[row];
+          const int node = src < r ? a : b;
+          v = seg_sum(segs, seg_start, node, elems, (src % r) + (int64_t)(cbase + c) * r);
+        }
+        x[s][c] = v;
+      }
+    }
+    wave_lu_solve<T, kCfCols, 0>(x, K, kud_s, n2, lane);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int row = s * 64 + lane;
+#pragma unroll
+      for (int c = 0; c < kCfCols; ++c)
+        if (row < n2 && cbase + c < Rp) Wg[row + (int64_t)(cbase + c) * n2] = x[s][c];
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_couple_factor(hipStream_t s, int nparents, int r, int Rp, const T* segs,
+                                const int32_t* d_seg_start, T* Klu, int32_t* Kpiv, int32_t* Kperm, T* Kud, T* W,
+                                unsigned long long* info, int level, int L) {
+  if (nparents == 0 || r == 0) return hipSuccess;
+  const size_t smem = sizeof(T) * ((size_t)4 * r * r + 2 * r);
+  auto k = couple_factor_kernel<T>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(nparents), dim3(kCfThreads), smem, s, r, Rp, segs, d_seg_start, Klu, Kpiv, Kperm, Kud,
+                     W, info, level, L);
+  return hipGetLastError();
+}
+template hipError_t launch_couple_factor<double>(hipStream_t, int, int, int, const double*, const int32_t*, double*,
+                                                 int32_t*, int32_t*, double*, double*, unsigned long long*, int, int);
+template hipError_t launch_couple_factor<float>(hipStream_t, int, int, int, const float*, const int32_t*, float*,
+                                                int32_t*, int32_t*, float*, float*, unsigned long long*, int, int);
+
+// ---------------------------------------------------------------------------
+// couple_solve: one wave per parent, columns in groups of kCsCols
+// ---------------------------------------------------------------------------
+constexpr int kCsCols = 4;
+
+template <typename T, int TRANS>
+__global__ __launch_bounds__(64) void couple_solve_kernel(int r, int nrhs, const T* __restrict__ segs,
+                                                          const int32_t* __restrict__ seg_start,
+                                                          const T* __restrict__ Klu, const int32_t* __restrict__ Kperm,
+                                                          const T* __restrict__ Kud, T* __restrict__ w) {
+  const int g = blockIdx.x;
+  const int a = 2 * g, b = 2 * g + 1;
+  const int n2 = 2 * r;
+  const int lane = threadIdx.x;
+  const int64_t elems = (int64_t)r * nrhs;
+  const T* Kf = Klu + (int64_t)g * n2 * n2;
+  const int32_t* pm = Kperm + (int64_t)g * n2;
+  const T* kud = Kud + (int64_t)g * n2;
+  T* wg = w + (int64_t)g * n2 * nrhs;
+  for (int cbase = 0; cbase < nrhs; cbase += kCsCols) {
+    T x[2][kCsCols];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int row = s * 64 + lane;
+#pragma unroll
+      for (int c = 0; c < kCsCols; ++c) {
+        T v = T(0);
+        if (row < n2 && cbase + c < nrhs) {
+          const int src = TRANS ? row : pm[row];
+          const int node = src < r ? a : b;
+          v = seg_sum(segs, seg_start, node, elems, (src % r) + (int64_t)(cbase + c) * r);
+        }
+        x[s][c] = v;
+      }
+    }
+    wave_lu_solve<T, kCsCols, TRANS>(x, Kf, kud, n2, lane);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int row = s * 64 + lane;
+#pragma unroll
+      for (int c = 0; c < kCsCols; ++c)
+        if (row < n2 && cbase + c < nrhs) {
+          const int dst = TRANS ? pm[row] : row;
+          wg[dst + (int64_t)(cbase + c) * n2] = x[s][c];
+        }
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_couple_solve(hipStream_t s, int trans, int nparents, int r, int nrhs, const T* segs,
+                               const int32_t* d_seg_start, const T* Klu, const int32_t* Kperm, const T* Kud, T* w) {
+  if (nparents == 0 || r == 0 || nrhs == 0) return hipSuccess;
+  if (trans)
+    hipLaunchKernelGGL((couple_solve_kernel<T, 1>), dim3(nparents), dim3(64), 0, s, r, nrhs, segs, d_seg_start,
+                       Klu, Kperm, Kud, w);
+  else
+    hipLaunchKernelGGL((couple_solve_kernel<T, 0>), dim3(nparents), dim3(64), 0, s, r, nrhs, segs, d_seg_start,
+                       Klu, Kperm, Kud, w);
+  return hipGetLastError();
+}
+template hipError_t launch_couple_solve<double>(hipStream_t, int, int, int, int, const double*, const int32_t*,
+                                                const double*, const int32_t*, const double*, double*);
+template hipError_t launch_couple_solve<float>(hipStream_t, int, int, int, int, const float*, const int32_t*,
+                                               const float*, const int32_t*, const float*, float*);
+
+}  // namespace hodlr

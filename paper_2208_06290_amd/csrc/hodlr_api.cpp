@@ -1,0 +1,933 @@
+// C ABI of the HODLR library: argument checking, the integer plan (tree,
+// row tiles, reduction segments), device memory, and the level-synchronous
+// orchestration of the kernels (Section III-C: the cluster tree is the task
+// graph, nodes of one level are independent, each level waits for the one
+// below).  Every launch goes to the caller's stream; the only host
+// synchronisations are the singularity verdict of a factorization and the
+// residual norm of each refinement step.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+using namespace hodlr;
+
+// ---------------------------------------------------------------------------
+// per-kernel timing with HIP events on the launch stream
+// ---------------------------------------------------------------------------
+namespace {
+struct TimeRec {
+  const char* name;
+  hipEvent_t e0, e1;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimeRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+std::map<std::string, std::pair<double, int64_t>> g_tot;
+
+hipEvent_t pool_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  hipEventCreate(&e);
+  return e;
+}
+void drain_records() {
+  for (auto& r : g_recs) {
+    float ms = 0.f;
+    hipEventSynchronize(r.e1);
+    hipEventElapsedTime(&ms, r.e0, r.e1);
+    auto& t = g_tot[r.name];
+    t.first += ms;
+    t.second += 1;
+    g_pool.push_back(r.e0);
+    g_pool.push_back(r.e1);
+  }
+  g_recs.clear();
+}
+
+struct TimerScope {
+  hipStream_t s;
+  const char* name;
+  hipEvent_t e1 = nullptr;
+  hipEvent_t e0 = nullptr;
+  bool on;
+  TimerScope(hipStream_t s_, const char* n) : s(s_), name(n) {
+    std::lock_guard<std::mutex> g(g_tmu);
+    on = g_timing;
+    if (on) {
+      e0 = pool_event();
+      e1 = pool_event();
+      hipEventRecord(e0, s);
+    }
+  }
+  ~TimerScope() {
+    if (!on) return;
+    std::lock_guard<std::mutex> g(g_tmu);
+    hipEventRecord(e1, s);
+    g_recs.push_back({name, e0, e1});
+    if (g_recs.size() > 4096) drain_records();
+  }
+};
+}  // namespace
+
+#define HL(name, call)                                     \
+  do {                                                     \
+    TimerScope _ts(st, name);                              \
+    hipError_t _e = (call);                                \
+    if (_e != hipSuccess) return hip_fail(_e, name);       \
+  } while (0)
+
+static hodlr_status hip_fail(hipError_t e, const char* what) {
+  if (getenv("HODLR_VERBOSE")) fprintf(stderr, "hodlr: %s failed: %s\n", what, hipGetErrorString(e));
+  return HODLR_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// plan and factor object
+// ---------------------------------------------------------------------------
+namespace {
+
+struct DevMem {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  template <typename X>
+  hodlr_status alloc(X** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return HODLR_OK;
+    void* q = nullptr;
+    if (hipMalloc(&q, count * sizeof(X)) != hipSuccess) return HODLR_ERR_ALLOC;
+    ptrs.push_back(q);
+    bytes += count * sizeof(X);
+    *p = static_cast<X*>(q);
+    return HODLR_OK;
+  }
+  void release() {
+    for (void* p : ptrs) hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+};
+
+// Reduction plan of a product whose node level is p, computed on tiles of level q >= p.
+struct ProdPlan {
+  int nnodes = 0;
+  bool reduced = false;
+  int nsegs = 0;
+  int maxcount = 0;
+  int32_t* d_seg_start = nullptr;
+  int2* d_desc = nullptr;
+};
+
+}  // namespace
+
+struct hodlr_factors {
+  // shape
+  int64_t n = 0;
+  int L = 0;
+  int nleaf = 1;
+  int m_max = 0;
+  int ldl = 0;  // leaf factor block size: m_max rounded up to a multiple of 16
+  int R = 0;
+  std::vector<int64_t> off;
+  std::vector<int> ranks;  // r_1..r_L
+  std::vector<int> Rp;     // R_0..R_L
+  hodlr_dtype storage = HODLR_F64, compute = HODLR_F64;
+  // the caller's matrix
+  const void *D = nullptr, *U = nullptr, *V = nullptr;
+  int64_t ldd = 0, ldu = 0, ldv = 0;
+  // device plan
+  DevMem mem;
+  int64_t* d_off = nullptr;
+  int32_t* d_rpre = nullptr;
+  std::vector<Tile*> d_tiles;                 // per tile level q = 0..L
+  std::vector<int> ntiles;                    // per q
+  std::vector<std::vector<int>> tile_start;   // per q, 2^q + 1
+  std::map<std::pair<int, int>, ProdPlan> prods;
+  // factors (T = compute element type)
+  size_t tsize = 8;
+  void* lu = nullptr;
+  int32_t* piv = nullptr;
+  int32_t* perm = nullptr;
+  void* udinv = nullptr;
+  void* Y = nullptr;
+  std::vector<int64_t> koff, kvoff;  // per parent level p: element offsets of K blocks / K vectors
+  void* Klu = nullptr;
+  int32_t* Kpiv = nullptr;
+  int32_t* Kperm = nullptr;
+  void* Kud = nullptr;
+  // factor workspace
+  void* W = nullptr;
+  void* P = nullptr;
+  void* segbuf = nullptr;
+  unsigned long long* d_info = nullptr;
+  // solve / matvec / refinement workspace, grown on demand
+  DevMem ws;
+  int ws_nrhs = -1;
+  void* sP = nullptr;
+  void* sseg = nullptr;
+  void* sw = nullptr;
+  void* sx = nullptr;      // compute-type copy of the right-hand sides
+  double* rx = nullptr;    // refinement: iterate x
+  double* rr = nullptr;    // refinement: residual
+  double* tree = nullptr;  // matvec projection tree
+  double* tree2 = nullptr;
+  double* nrm = nullptr;   // norms: part | b2 | r2 | rinf
+  std::mutex mu;
+};
+
+namespace {
+
+int ilog2(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
+
+hodlr_status validate(const hodlr_matrix* A, std::vector<int64_t>& off, std::vector<int>& ranks, int& m_max) {
+  if (!A || A->n < 1 || A->levels < 0 || A->levels > HODLR_MAX_LEVELS) return HODLR_ERR_ARG;
+  const int L = A->levels;
+  const int64_t nl = int64_t(1) << L;
+  if (nl > A->n) return HODLR_ERR_ARG;
+  off.assign(nl + 1, 0);
+  if (A->leaf_offsets) {
+    for (int64_t i = 0; i <= nl; ++i) off[i] = A->leaf_offsets[i];
+    if (off[0] != 0 || off[nl] != A->n) return HODLR_ERR_ARG;
+    for (int64_t i = 0; i < nl; ++i)
+      if (off[i + 1] <= off[i]) return HODLR_ERR_ARG;
+  } else {
+    if (A->n % nl) return HODLR_ERR_ARG;
+    for (int64_t i = 0; i <= nl; ++i) off[i] = i * (A->n / nl);
+  }
+  m_max = 0;
+  for (int64_t i = 0; i < nl; ++i) m_max = (int)std::max<int64_t>(m_max, off[i + 1] - off[i]);
+  if (m_max > HODLR_MAX_LEAF) return HODLR_ERR_UNSUPPORTED;
+  ranks.assign(L, 0);
+  if (L > 0 && !A->ranks) return HODLR_ERR_ARG;
+  for (int l = 0; l < L; ++l) {
+    if (A->ranks[l] < 0) return HODLR_ERR_ARG;
+    if (A->ranks[l] > HODLR_MAX_RANK) return HODLR_ERR_UNSUPPORTED;
+    ranks[l] = A->ranks[l];
+  }
+  if (A->dtype != HODLR_F64 && A->dtype != HODLR_F32) return HODLR_ERR_ARG;
+  int R = 0;
+  for (int r : ranks) R += r;
+  if (!A->D || A->ldd < A->n) return HODLR_ERR_ARG;
+  if (R > 0 && (!A->U || !A->V || A->ldu < A->n || A->ldv < A->n)) return HODLR_ERR_ARG;
+  return HODLR_OK;
+}
+
+// tiles of level q: every level-q node split into runs of <= kTileRows rows
+void build_tiles(hodlr_factors* F, int q, std::vector<Tile>& out, std::vector<int>& start) {
+  const int per = 1 << (F->L - q);
+  const int nn = 1 << q;
+  start.assign(nn + 1, 0);
+  out.clear();
+  for (int i = 0; i < nn; ++i) {
+    start[i] = (int)out.size();
+    const int64_t s = F->off[(int64_t)i * per], e = F->off[(int64_t)(i + 1) * per];
+    for (int64_t r = s; r < e; r += kTileRows) out.push_back(Tile{r, (int32_t)std::min<int64_t>(kTileRows, e - r), i});
+  }
+  start[nn] = (int)out.size();
+}
+
+hodlr_status make_prod(hodlr_factors* F, int q, int p, hipStream_t st) {
+  auto key = std::make_pair(q, p);
+  if (F->prods.count(key)) return HODLR_OK;
+  ProdPlan pp;
+  pp.nnodes = 1 << p;
+  const int stride = 1 << (q - p);
+  const std::vector<int>& ts = F->tile_start[q];
+  std::vector<int32_t> seg_start(pp.nnodes + 1, 0);
+  std::vector<int2> desc;
+  for (int i = 0; i < pp.nnodes; ++i) pp.maxcount = std::max(pp.maxcount, ts[(i + 1) * stride] - ts[i * stride]);
+  pp.reduced = pp.maxcount > kSegTiles;
+  for (int i = 0; i < pp.nnodes; ++i) {
+    const int t0 = ts[i * stride], t1 = ts[(i + 1) * stride];
+    if (!pp.reduced) {
+      seg_start[i] = t0;
+      continue;
+    }
+    seg_start[i] = (int)desc.size();
+    for (int t = t0; t < t1; t += kSegTiles) desc.push_back(int2{t, std::min(kSegTiles, t1 - t)});
+  }
+  seg_start[pp.nnodes] = pp.reduced ? (int)desc.size() : ts[pp.nnodes * stride];
+  pp.nsegs = pp.reduced ? (int)desc.size() : 0;
+  hodlr_status s = F->mem.alloc(&pp.d_seg_start, seg_start.size());
+  if (s) return s;
+  if (hipMemcpy(pp.d_seg_start, seg_start.data(), seg_start.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return HODLR_ERR_HIP;
+  if (pp.reduced) {
+    s = F->mem.alloc(&pp.d_desc, desc.size());
+    if (s) return s;
+    if (hipMemcpy(pp.d_desc, desc.data(), desc.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+      return HODLR_ERR_HIP;
+  }
+  F->prods[key] = pp;
+  (void)st;
+  return HODLR_OK;
+}
+
+// tile level on which the product of node level p is computed
+int fwd_prod_tiles(const hodlr_factors* F, int p) { return p == F->L ? F->L : p + 1; }
+int adj_prod_tiles(const hodlr_factors*, int p) { return p; }
+
+hodlr_status plan(hodlr_factors* F) {
+  const int L = F->L;
+  F->d_tiles.assign(L + 1, nullptr);
+  F->ntiles.assign(L + 1, 0);
+  F->tile_start.assign(L + 1, {});
+  std::vector<Tile> tl;
+  for (int q = 0; q <= L; ++q) {
+    build_tiles(F, q, tl, F->tile_start[q]);
+    F->ntiles[q] = (int)tl.size();
+    hodlr_status s = F->mem.alloc(&F->d_tiles[q], tl.size());
+    if (s) return s;
+    if (hipMemcpy(F->d_tiles[q], tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess)
+      return HODLR_ERR_HIP;
+  }
+  for (int p = 1; p <= L; ++p) {
+    hodlr_status s = make_prod(F, fwd_prod_tiles(F, p), p, nullptr);
+    if (s) return s;
+    s = make_prod(F, adj_prod_tiles(F, p), p, nullptr);
+    if (s) return s;
+  }
+  return HODLR_OK;
+}
+
+size_t tsz(hodlr_dtype c) { return c == HODLR_F64 ? 8 : 4; }
+
+hodlr_status allocate_factors(hodlr_factors* F) {
+  DevMem& M = F->mem;
+  const int L = F->L;
+  const size_t ts = F->tsize;
+  hodlr_status s;
+  if ((s = M.alloc(&F->d_off, F->off.size()))) return s;
+  if (hipMemcpy(F->d_off, F->off.data(), F->off.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return HODLR_ERR_HIP;
+  std::vector<int32_t> rp(F->Rp.begin(), F->Rp.end());
+  if ((s = M.alloc(&F->d_rpre, rp.size()))) return s;
+  if (hipMemcpy(F->d_rpre, rp.data(), rp.size() * 4, hipMemcpyHostToDevice) != hipSuccess) return HODLR_ERR_HIP;
+  if ((s = plan(F))) return s;
+  unsigned char* b;
+  const size_t nl = F->nleaf, mm = F->ldl;
+  if ((s = M.alloc(&b, nl * mm * mm * ts))) return s;
+  F->lu = b;
+  if ((s = M.alloc(&F->piv, nl * mm))) return s;
+  if ((s = M.alloc(&F->perm, nl * mm))) return s;
+  if ((s = M.alloc(&b, nl * mm * ts))) return s;
+  F->udinv = b;
+  if ((s = M.alloc(&b, (size_t)F->n * F->R * ts))) return s;
+  F->Y = b;
+  F->koff.assign(L + 1, 0);
+  F->kvoff.assign(L + 1, 0);
+  int64_t kk = 0, kv = 0;
+  size_t wmax = 0, pmax = 0, segmax = 0;
+  for (int p = 0; p < L; ++p) {
+    const int r = F->ranks[p];  // r_{p+1}
+    F->koff[p] = kk;
+    F->kvoff[p] = kv;
+    kk += (int64_t(1) << p) * 4 * r * r;
+    kv += (int64_t(1) << p) * 2 * r;
+    wmax = std::max(wmax, (size_t)(int64_t(1) << p) * 2 * r * F->Rp[p]);
+  }
+  F->koff[L] = kk;
+  F->kvoff[L] = kv;
+  for (int p = 1; p <= L; ++p) {
+    const int q = fwd_prod_tiles(F, p);
+    const size_t elems = (size_t)F->ranks[p - 1] * F->Rp[p];
+    pmax = std::max(pmax, (size_t)F->ntiles[q] * elems);
+    const ProdPlan& pp = F->prods[{q, p}];
+    if (pp.reduced) segmax = std::max(segmax, (size_t)pp.nsegs * elems);
+  }
+  if ((s = M.alloc(&b, (size_t)kk * ts))) return s;
+  F->Klu = b;
+  if ((s = M.alloc(&F->Kpiv, (size_t)kv))) return s;
+  if ((s = M.alloc(&F->Kperm, (size_t)kv))) return s;
+  if ((s = M.alloc(&b, (size_t)kv * ts))) return s;
+  F->Kud = b;
+  if ((s = M.alloc(&b, wmax * ts))) return s;
+  F->W = b;
+  if ((s = M.alloc(&b, pmax * ts))) return s;
+  F->P = b;
+  if ((s = M.alloc(&b, segmax * ts))) return s;
+  F->segbuf = b;
+  if ((s = M.alloc(&F->d_info, 2))) return s;
+  return HODLR_OK;
+}
+
+template <typename T>
+T* tp(void* p) {
+  return static_cast<T*>(p);
+}
+
+// segments for the product of node level p on tile level q (reduces if needed)
+template <typename T>
+hodlr_status prod_segments(hodlr_factors* F, hipStream_t st, int q, int p, int64_t elems, T* P, T* segbuf,
+                           const T** segs, const int32_t** seg_start) {
+  const ProdPlan& pp = F->prods.at({q, p});
+  if (pp.reduced) {
+    HL("segment_reduce", launch_segment_reduce<T>(st, pp.nsegs, pp.d_desc, elems, P, segbuf));
+    *segs = segbuf;
+  } else {
+    *segs = P;
+  }
+  *seg_start = pp.d_seg_start;
+  return HODLR_OK;
+}
+
+template <typename T, typename S>
+hodlr_status run_factor(hodlr_factors* F, hipStream_t st) {
+  const int L = F->L;
+  const int64_t N = F->n;
+  T* Y = tp<T>(F->Y);
+  const S* D = static_cast<const S*>(F->D);
+  const S* U = static_cast<const S*>(F->U);
+  const S* V = static_cast<const S*>(F->V);
+  if (hipMemsetAsync(F->d_info, 0xFF, 2 * sizeof(unsigned long long), st) != hipSuccess) return HODLR_ERR_HIP;
+  HL("leaf_lu", (launch_leaf_lu<T, S>(st, F->nleaf, F->ldl, F->d_off, D, F->ldd, tp<T>(F->lu), F->piv, F->perm,
+                                      tp<T>(F->udinv), F->d_info)));
+  if (F->R > 0)
+    HL("leaf_trsm", (launch_leaf_trsm<T, S>(st, 0, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->perm,
+                                            tp<T>(F->udinv), U, F->ldu, Y, N, F->R)));
+  if (L > 0) {
+    // products V^T Y for the children of level L-1 (the leaves)
+    HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], Y, N, F->R, (const T*)nullptr, N, 0,
+                                                 (const T*)nullptr, 0, 0, 0, V + (int64_t)F->Rp[L - 1] * F->ldv,
+                                                 F->ldv, F->ranks[L - 1], tp<T>(F->P))));
+    for (int p = L - 1; p >= 0; --p) {
+      const int q = p + 1;
+      const int r = F->ranks[q - 1];
+      const int Rp = F->Rp[p];
+      const T* segs;
+      const int32_t* seg_start;
+      hodlr_status s = prod_segments<T>(F, st, fwd_prod_tiles(F, q), q, (int64_t)r * F->Rp[q], tp<T>(F->P),
+                                        tp<T>(F->segbuf), &segs, &seg_start);
+      if (s) return s;
+      HL("couple_factor", (launch_couple_factor<T>(st, 1 << p, r, Rp, segs, seg_start, tp<T>(F->Klu) + F->koff[p],
+                                                   F->Kpiv + F->kvoff[p], F->Kperm + F->kvoff[p],
+                                                   tp<T>(F->Kud) + F->kvoff[p], tp<T>(F->W), F->d_info + 1, p, L)));
+      if (p > 0 && r > 0) {
+        HL("level_pass",
+           (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], Y, N, Rp, Y + (int64_t)Rp * N, N, r,
+                                       tp<T>(F->W), 2 * r, (int64_t)2 * r * Rp, 0,
+                                       V + (int64_t)F->Rp[p - 1] * F->ldv, F->ldv, F->ranks[p - 1], tp<T>(F->P))));
+      } else if (p > 0) {
+        // rank-0 children: no update; products for level p still needed
+        HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], Y, N, Rp, (const T*)nullptr, N,
+                                                     0, (const T*)nullptr, 0, 0, 0,
+                                                     V + (int64_t)F->Rp[p - 1] * F->ldv, F->ldv, F->ranks[p - 1],
+                                                     tp<T>(F->P))));
+      }
+    }
+  }
+  return HODLR_OK;
+}
+
+hodlr_status verdict(hodlr_factors* F, hipStream_t st, hodlr_info* info) {
+  unsigned long long h[2];
+  if (hipMemcpyAsync(h, F->d_info, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return HODLR_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return HODLR_ERR_HIP;
+  if (info) {
+    info->level = -1;
+    info->column = -1;
+    info->node = -1;
+  }
+  if (h[0] != ~0ull) {
+    if (info) {
+      info->level = F->L;
+      info->node = (int64_t)(h[0] >> 20);
+      info->column = (int32_t)(h[0] & 0xFFFFF);
+    }
+    return HODLR_ERR_SINGULAR;
+  }
+  if (h[1] != ~0ull) {
+    if (info) {
+      info->level = F->L - (int32_t)(h[1] >> 44);
+      info->node = (int64_t)((h[1] >> 16) & 0xFFFFFFF);
+      info->column = (int32_t)(h[1] & 0xFFFF);
+    }
+    return HODLR_ERR_SINGULAR;
+  }
+  return HODLR_OK;
+}
+
+hodlr_status dispatch_factor(hodlr_factors* F, hipStream_t st) {
+  if (F->compute == HODLR_F64) return run_factor<double, double>(F, st);
+  if (F->storage == HODLR_F64) return run_factor<float, double>(F, st);
+  return run_factor<float, float>(F, st);
+}
+
+// ---- solve-side workspace --------------------------------------------------
+hodlr_status ensure_ws(hodlr_factors* F, int nrhs) {
+  if (nrhs <= F->ws_nrhs) return HODLR_OK;
+  F->ws.release();
+  F->ws_nrhs = -1;
+  const int L = F->L;
+  const size_t ts = F->tsize;
+  size_t pmax = 0, segmax = 0, wmax = 0;
+  for (int p = 1; p <= L; ++p) {
+    const size_t elems = (size_t)F->ranks[p - 1] * nrhs;
+    for (int q : {fwd_prod_tiles(F, p), adj_prod_tiles(F, p)}) {
+      pmax = std::max(pmax, (size_t)F->ntiles[q] * elems);
+      const ProdPlan& pp = F->prods[{q, p}];
+      if (pp.reduced) segmax = std::max(segmax, (size_t)pp.nsegs * elems);
+    }
+  }
+  for (int p = 0; p < L; ++p) wmax = std::max(wmax, (size_t)(int64_t(1) << p) * 2 * F->ranks[p] * nrhs);
+  const size_t n = (size_t)F->n * nrhs;
+  const size_t treeN = (((size_t)1 << (L + 1)) - 2) * (size_t)std::max(F->R, 1) * nrhs;
+  unsigned char* b;
+  hodlr_status s;
+  DevMem& M = F->ws;
+  if ((s = M.alloc(&b, pmax * ts))) return s;
+  F->sP = b;
+  if ((s = M.alloc(&b, segmax * ts))) return s;
+  F->sseg = b;
+  if ((s = M.alloc(&b, wmax * ts))) return s;
+  F->sw = b;
+  if ((s = M.alloc(&b, n * ts))) return s;
+  F->sx = b;
+  if ((s = M.alloc(&F->rx, n))) return s;
+  if ((s = M.alloc(&F->rr, n))) return s;
+  if ((s = M.alloc(&F->tree, std::max<size_t>(treeN, 1)))) return s;
+  if ((s = M.alloc(&F->tree2, std::max<size_t>(treeN, 1)))) return s;
+  if ((s = M.alloc(&F->nrm, (size_t)nrhs * (2 * 256 + 8)))) return s;
+  F->ws_nrhs = nrhs;
+  return HODLR_OK;
+}
+
+// x <- A^{-1} x (trans = 0) or A^{-T} x (trans = 1) in the compute precision, x: N x nrhs, ld N
+template <typename T, typename S>
+hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs, T* X, int64_t ldx) {
+  const int L = F->L;
+  const int64_t N = F->n;
+  const T* Y = tp<T>(F->Y);
+  const S* V = static_cast<const S*>(F->V);
+  T* P = tp<T>(F->sP);
+  T* w = tp<T>(F->sw);
+  if (!trans) {
+    HL("leaf_solve", (launch_leaf_trsm<T, T>(st, 0, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->perm,
+                                             tp<T>(F->udinv), X, ldx, X, ldx, nrhs)));
+    if (L == 0) return HODLR_OK;
+    HL("solve_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], X, ldx, nrhs, (const T*)nullptr, N,
+                                                 0, (const T*)nullptr, 0, 0, 0, V + (int64_t)F->Rp[L - 1] * F->ldv,
+                                                 F->ldv, F->ranks[L - 1], P)));
+    for (int p = L - 1; p >= 0; --p) {
+      const int q = p + 1;
+      const int r = F->ranks[q - 1];
+      if (r > 0) {
+        const T* segs;
+        const int32_t* seg_start;
+        hodlr_status s = prod_segments<T>(F, st, fwd_prod_tiles(F, q), q, (int64_t)r * nrhs, P, tp<T>(F->sseg),
+                                          &segs, &seg_start);
+        if (s) return s;
+        HL("couple_solve", (launch_couple_solve<T>(st, 0, 1 << p, r, nrhs, segs, seg_start,
+                                                   tp<T>(F->Klu) + F->koff[p], F->Kperm + F->kvoff[p],
+                                                   tp<T>(F->Kud) + F->kvoff[p], w)));
+      }
+      const int kb = p > 0 ? F->ranks[p - 1] : 0;
+      if (r == 0 && kb == 0) continue;
+      HL("solve_pass", (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], X, ldx, nrhs,
+                                                   Y + (int64_t)F->Rp[p] * N, N, r, w, 2 * r, (int64_t)2 * r * nrhs, 0,
+                                                   p > 0 ? V + (int64_t)F->Rp[p - 1] * F->ldv : nullptr, F->ldv, kb,
+                                                   P)));
+    }
+    return HODLR_OK;
+  }
+  // adjoint: top level first, transposed coupling solves, leaves last
+  if (L > 0) {
+    HL("adjoint_pass", (launch_level_pass<T, S, T>(st, F->ntiles[1], F->d_tiles[1], X, ldx, nrhs, (const S*)nullptr,
+                                                   N, 0, (const T*)nullptr, 0, 0, 0, Y, N, F->ranks[0], P)));
+    for (int p = 0; p < L; ++p) {
+      const int q = p + 1;
+      const int r = F->ranks[q - 1];
+      if (r > 0) {
+        const T* segs;
+        const int32_t* seg_start;
+        hodlr_status s = prod_segments<T>(F, st, adj_prod_tiles(F, q), q, (int64_t)r * nrhs, P, tp<T>(F->sseg),
+                                          &segs, &seg_start);
+        if (s) return s;
+        HL("couple_solve_t", (launch_couple_solve<T>(st, 1, 1 << p, r, nrhs, segs, seg_start,
+                                                     tp<T>(F->Klu) + F->koff[p], F->Kperm + F->kvoff[p],
+                                                     tp<T>(F->Kud) + F->kvoff[p], w)));
+      }
+      const int tq = q < L ? q + 1 : L;
+      const int kb = q < L ? F->ranks[q] : 0;
+      if (r == 0 && kb == 0) continue;
+      HL("adjoint_pass", (launch_level_pass<T, S, T>(st, F->ntiles[tq], F->d_tiles[tq], X, ldx, nrhs,
+                                                     V + (int64_t)F->Rp[p] * F->ldv, F->ldv, r, w, 2 * r,
+                                                     (int64_t)2 * r * nrhs, tq - q,
+                                                     q < L ? Y + (int64_t)F->Rp[q] * N : nullptr, N, kb, P)));
+    }
+  }
+  HL("leaf_solve_t", (launch_leaf_trsm<T, T>(st, 1, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->perm,
+                                             tp<T>(F->udinv), X, ldx, X, ldx, nrhs)));
+  return HODLR_OK;
+}
+
+// Y = op(A) X in FP64 from the caller's D, U, V (storage type S); tree: projection workspace
+template <typename S>
+hodlr_status matvec_impl(hodlr_factors* F, hipStream_t st, int trans, int nrhs, const double* X, int64_t ldx,
+                         double* Yo, int64_t ldy, double* tree) {
+  const int L = F->L;
+  const S* Ua = static_cast<const S*>(trans ? F->V : F->U);
+  const S* Vb = static_cast<const S*>(trans ? F->U : F->V);
+  const int64_t lda = trans ? F->ldv : F->ldu, ldb = trans ? F->ldu : F->ldv;
+  if (L > 0 && F->R > 0) {
+    double* leaves = tree + tree_slot(L, 0) * F->R * nrhs;
+    HL("mv_project", (launch_level_pass<double, double, S>(st, F->ntiles[L], F->d_tiles[L], const_cast<double*>(X),
+                                                           ldx, nrhs, (const double*)nullptr, 0, 0,
+                                                           (const double*)nullptr, 0, 0, 0, Vb, ldb, F->R, leaves)));
+    for (int l = L - 1; l >= 1; --l)
+      HL("mv_tree", launch_tree_sum(st, 1 << l, (int64_t)F->R * nrhs, tree + tree_slot(l + 1, 0) * F->R * nrhs,
+                                    tree + tree_slot(l, 0) * F->R * nrhs));
+  }
+  HL("mv_apply", (launch_matvec_apply<S>(st, trans, F->nleaf, L, F->d_off, F->d_rpre, F->R,
+                                         static_cast<const S*>(F->D), F->ldd, Ua, lda, X, ldx, tree, Yo, ldy, nrhs)));
+  return HODLR_OK;
+}
+
+hodlr_status matvec_dispatch(hodlr_factors* F, hipStream_t st, int trans, int nrhs, const double* X, int64_t ldx,
+                             double* Yo, int64_t ldy, double* tree) {
+  if (F->storage == HODLR_F64) return matvec_impl<double>(F, st, trans, nrhs, X, ldx, Yo, ldy, tree);
+  return matvec_impl<float>(F, st, trans, nrhs, X, ldx, Yo, ldy, tree);
+}
+
+template <typename T>
+hodlr_status inverse_dispatch(hodlr_factors* F, hipStream_t st, int trans, int nrhs, T* X, int64_t ldx) {
+  // FP64 factors exist only for FP64 storage (checked at factorization)
+  if constexpr (sizeof(T) == 8) {
+    return apply_inverse<double, double>(F, st, trans, nrhs, X, ldx);
+  } else {
+    if (F->storage == HODLR_F64) return apply_inverse<float, double>(F, st, trans, nrhs, X, ldx);
+    return apply_inverse<float, float>(F, st, trans, nrhs, X, ldx);
+  }
+}
+
+template <typename T>
+hodlr_status solve_impl(hodlr_factors* F, int trans, int nrhs, double* B, int64_t ldb, const hodlr_solve_opts* o,
+                        hipStream_t st, hodlr_solve_stats* stt) {
+  const int64_t N = F->n;
+  hodlr_status s = ensure_ws(F, nrhs);
+  if (s) return s;
+  if (stt) {
+    stt->iters = 0;
+    stt->converged = 1;
+    stt->relres = 0.0;
+  }
+  const bool refine = o && o->refine;
+  if (!refine) {
+    if (sizeof(T) == 8) return inverse_dispatch<T>(F, st, trans, nrhs, reinterpret_cast<T*>(B), ldb);
+    T* x = tp<T>(F->sx);
+    HL("convert", (launch_convert<T, double>(st, N, nrhs, B, ldb, x, N)));
+    s = inverse_dispatch<T>(F, st, trans, nrhs, x, N);
+    if (s) return s;
+    HL("convert", (launch_convert<double, T>(st, N, nrhs, x, N, B, ldb)));
+    return HODLR_OK;
+  }
+  // FP64 iterative refinement
+  const double tol = o->tol > 0 ? o->tol : 1e-10;
+  const int max_iter = o->max_iter > 0 ? o->max_iter : 30;
+  double* part = F->nrm;
+  double* b2 = part + (size_t)nrhs * 512;
+  double* r2 = b2 + nrhs;
+  double* rinf = r2 + nrhs;
+  double* x = F->rx;
+  double* r = F->rr;
+  T* t = tp<T>(F->sx);
+  HL("norms", launch_colnorms(st, N, nrhs, B, ldb, part, b2, rinf));
+  if (hipMemsetAsync(x, 0, (size_t)N * nrhs * 8, st) != hipSuccess) return HODLR_ERR_HIP;
+  if (hipMemcpy2DAsync(r, N * 8, B, ldb * 8, N * 8, nrhs, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return HODLR_ERR_HIP;
+  std::vector<double> hb(nrhs), hr(nrhs);
+  if (hipMemcpyAsync(hb.data(), b2, nrhs * 8, hipMemcpyDeviceToHost, st) != hipSuccess) return HODLR_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return HODLR_ERR_HIP;
+  double prev = INFINITY, res = 0.0;
+  int grow = 0, it = 0;
+  for (int j = 0; j < nrhs; ++j) res = std::max(res, 1.0);  // r = b initially
+  if (nrhs == 0) res = 0.0;
+  while (res > tol && it < max_iter) {
+    HL("refine_scale", (launch_scale_down<T>(st, N, nrhs, r, N, rinf, t, N)));
+    s = inverse_dispatch<T>(F, st, trans, nrhs, t, N);
+    if (s) return s;
+    HL("refine_axpy", (launch_axpy_up<T>(st, N, nrhs, t, N, rinf, x, N)));
+    s = matvec_dispatch(F, st, trans, nrhs, x, N, r, N, F->tree);
+    if (s) return s;
+    HL("refine_residual", launch_residual(st, N, nrhs, B, ldb, r, N));
+    HL("norms", launch_colnorms(st, N, nrhs, r, N, part, r2, rinf));
+    if (hipMemcpyAsync(hr.data(), r2, nrhs * 8, hipMemcpyDeviceToHost, st) != hipSuccess) return HODLR_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return HODLR_ERR_HIP;
+    ++it;
+    res = 0.0;
+    for (int j = 0; j < nrhs; ++j) {
+      const double rj = hb[j] > 0 ? hr[j] / hb[j] : hr[j];
+      res = std::isfinite(rj) ? std::max(res, rj) : INFINITY;  // a NaN/Inf residual is divergence
+    }
+    grow = (res > prev) ? grow + 1 : 0;
+    prev = res;
+    if (grow >= 2) break;
+  }
+  if (hipMemcpy2DAsync(B, ldb * 8, x, N * 8, N * 8, nrhs, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return HODLR_ERR_HIP;
+  if (stt) {
+    stt->iters = it;
+    stt->relres = res;
+    stt->converged = res <= tol;
+  }
+  return res <= tol ? HODLR_OK : HODLR_ERR_NOT_CONVERGED;
+}
+
+hodlr_status solve_common(const hodlr_factors* Fc, int trans, int64_t nrhs, double* B, int64_t ldb,
+                          const hodlr_solve_opts* o, void* stream, hodlr_solve_stats* stt) {
+  hodlr_factors* F = const_cast<hodlr_factors*>(Fc);
+  if (!F || nrhs < 0 || nrhs > 65535 || (nrhs > 0 && (!B || ldb < F->n))) return HODLR_ERR_ARG;
+  if (nrhs == 0) return HODLR_OK;
+  std::lock_guard<std::mutex> g(F->mu);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (F->compute == HODLR_F64) return solve_impl<double>(F, trans, (int)nrhs, B, ldb, o, st, stt);
+  return solve_impl<float>(F, trans, (int)nrhs, B, ldb, o, st, stt);
+}
+
+hodlr_status setup(hodlr_factors* F, const hodlr_matrix* A, hodlr_dtype compute) {
+  std::vector<int64_t> off;
+  std::vector<int> ranks;
+  int m_max = 0;
+  hodlr_status s = validate(A, off, ranks, m_max);
+  if (s) return s;
+  if (compute == HODLR_BF16) return HODLR_ERR_UNSUPPORTED;
+  if (compute != HODLR_F64 && compute != HODLR_F32) return HODLR_ERR_ARG;
+  if (compute == HODLR_F64 && A->dtype != HODLR_F64) return HODLR_ERR_UNSUPPORTED;
+  F->n = A->n;
+  F->L = A->levels;
+  F->nleaf = 1 << F->L;
+  F->m_max = m_max;
+  F->ldl = (m_max + 15) & ~15;
+  F->off = off;
+  F->ranks = ranks;
+  F->Rp.assign(F->L + 1, 0);
+  for (int l = 1; l <= F->L; ++l) F->Rp[l] = F->Rp[l - 1] + ranks[l - 1];
+  F->R = F->Rp[F->L];
+  F->storage = A->dtype;
+  F->compute = compute;
+  F->tsize = tsz(compute);
+  F->D = A->D;
+  F->U = A->U;
+  F->V = A->V;
+  F->ldd = A->ldd;
+  F->ldu = A->ldu;
+  F->ldv = A->ldv;
+  return HODLR_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+hodlr_status hodlr_factor(const hodlr_matrix* A, hodlr_dtype compute, void* stream, hodlr_factors** out,
+                          hodlr_info* info) {
+  if (!out) return HODLR_ERR_ARG;
+  *out = nullptr;
+  hodlr_factors* F = new hodlr_factors();
+  hodlr_status s = setup(F, A, compute);
+  if (s == HODLR_OK) s = allocate_factors(F);
+  if (s != HODLR_OK) {
+    F->mem.release();
+    delete F;
+    return s;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  s = dispatch_factor(F, st);
+  if (s == HODLR_OK) s = verdict(F, st, info);
+  if (s < 0) {
+    hipStreamSynchronize(st);
+    F->mem.release();
+    delete F;
+    return s;
+  }
+  *out = F;
+  return s;
+}
+
+hodlr_status hodlr_refactor(hodlr_factors* F, const hodlr_matrix* A, void* stream, hodlr_info* info) {
+  if (!F || !A) return HODLR_ERR_ARG;
+  std::vector<int64_t> off;
+  std::vector<int> ranks;
+  int m_max = 0;
+  hodlr_status s = validate(A, off, ranks, m_max);
+  if (s) return s;
+  if (A->n != F->n || A->levels != F->L || off != F->off || ranks != F->ranks || A->dtype != F->storage ||
+      A->ldd != F->ldd || A->ldu != F->ldu || A->ldv != F->ldv)
+    return HODLR_ERR_ARG;
+  std::lock_guard<std::mutex> g(F->mu);
+  F->D = A->D;
+  F->U = A->U;
+  F->V = A->V;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  s = dispatch_factor(F, st);
+  if (s == HODLR_OK) s = verdict(F, st, info);
+  return s;
+}
+
+hodlr_status hodlr_solve(const hodlr_factors* F, int64_t nrhs, double* B, int64_t ldb, const hodlr_solve_opts* o,
+                         void* stream, hodlr_solve_stats* st) {
+  return solve_common(F, 0, nrhs, B, ldb, o, stream, st);
+}
+
+hodlr_status hodlr_solve_adjoint(const hodlr_factors* F, int64_t nrhs, double* B, int64_t ldb,
+                                 const hodlr_solve_opts* o, void* stream, hodlr_solve_stats* st) {
+  return solve_common(F, 1, nrhs, B, ldb, o, stream, st);
+}
+
+hodlr_status hodlr_matvec(const hodlr_matrix* A, int32_t trans, int64_t nrhs, const double* X, int64_t ldx, double* Yo,
+                          int64_t ldy, void* stream) {
+  if (nrhs < 0 || nrhs > 65535) return HODLR_ERR_ARG;
+  hodlr_factors F;
+  std::vector<int64_t> off;
+  std::vector<int> ranks;
+  int m_max = 0;
+  hodlr_status s = validate(A, off, ranks, m_max);
+  if (s) return s;
+  if (nrhs == 0) return HODLR_OK;
+  if (!X || !Yo || ldx < A->n || ldy < A->n) return HODLR_ERR_ARG;
+  s = setup(&F, A, A->dtype == HODLR_F64 ? HODLR_F64 : HODLR_F32);
+  if (s) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = F.mem.alloc(&F.d_off, F.off.size()))) return s;
+  std::vector<int32_t> rp(F.Rp.begin(), F.Rp.end());
+  s = F.mem.alloc(&F.d_rpre, rp.size());
+  if (!s && hipMemcpy(F.d_off, F.off.data(), F.off.size() * 8, hipMemcpyHostToDevice) != hipSuccess) s = HODLR_ERR_HIP;
+  if (!s && hipMemcpy(F.d_rpre, rp.data(), rp.size() * 4, hipMemcpyHostToDevice) != hipSuccess) s = HODLR_ERR_HIP;
+  if (!s) s = plan(&F);
+  double* tree = nullptr;
+  const size_t treeN = (((size_t)1 << (F.L + 1)) - 2) * (size_t)std::max(F.R, 1) * nrhs;
+  if (!s) s = F.mem.alloc(&tree, std::max<size_t>(treeN, 1));
+  if (!s) s = matvec_dispatch(&F, st, trans ? 1 : 0, (int)nrhs, X, ldx, Yo, ldy, tree);
+  hipStreamSynchronize(st);
+  F.mem.release();
+  return s;
+}
+
+hodlr_status hodlr_grad(const hodlr_factors* Fc, int64_t nrhs, const double* X, int64_t ldx, const double* Lam,
+                        int64_t ldl, void* dD, void* dU, void* dV, void* stream) {
+  hodlr_factors* F = const_cast<hodlr_factors*>(Fc);
+  if (!F || nrhs < 1 || nrhs > 65535 || !X || !Lam || ldx < F->n || ldl < F->n || !dD) return HODLR_ERR_ARG;
+  if (F->R > 0 && (!dU || !dV)) return HODLR_ERR_ARG;
+  std::lock_guard<std::mutex> g(F->mu);
+  hodlr_status s = ensure_ws(F, (int)nrhs);
+  if (s) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int L = F->L;
+  const int n = (int)nrhs;
+  auto project = [&](const void* Mv, int64_t ldm, const double* Xin, int64_t ldxin, double* tree) -> hodlr_status {
+    if (L == 0 || F->R == 0) return HODLR_OK;
+    double* leaves = tree + tree_slot(L, 0) * F->R * n;
+    if (F->storage == HODLR_F64)
+      HL("grad_project", (launch_level_pass<double, double, double>(
+                             st, F->ntiles[L], F->d_tiles[L], const_cast<double*>(Xin), ldxin, n, (const double*)nullptr,
+                             0, 0, (const double*)nullptr, 0, 0, 0, static_cast<const double*>(Mv), ldm, F->R, leaves)));
+    else
+      HL("grad_project", (launch_level_pass<double, double, float>(
+                             st, F->ntiles[L], F->d_tiles[L], const_cast<double*>(Xin), ldxin, n, (const double*)nullptr,
+                             0, 0, (const double*)nullptr, 0, 0, 0, static_cast<const float*>(Mv), ldm, F->R, leaves)));
+    for (int l = L - 1; l >= 1; --l)
+      HL("grad_tree", launch_tree_sum(st, 1 << l, (int64_t)F->R * n, tree + tree_slot(l + 1, 0) * F->R * n,
+                                      tree + tree_slot(l, 0) * F->R * n));
+    return HODLR_OK;
+  };
+  if ((s = project(F->V, F->ldv, X, ldx, F->tree))) return s;     // V^T X node sums
+  if ((s = project(F->U, F->ldu, Lam, ldl, F->tree2))) return s;  // U^T Lambda node sums
+  if (F->storage == HODLR_F64) {
+    HL("grad_leaf", (launch_grad_leaf<double>(st, F->nleaf, F->m_max, F->d_off, n, X, ldx, Lam, ldl,
+                                              static_cast<double*>(dD), F->ldd)));
+    if (F->R > 0 && L > 0) {
+      HL("grad_gen", (launch_grad_gen<double>(st, F->nleaf, L, F->d_off, F->d_rpre, F->R, n, Lam, ldl, F->tree,
+                                              static_cast<double*>(dU), F->ldu)));
+      HL("grad_gen", (launch_grad_gen<double>(st, F->nleaf, L, F->d_off, F->d_rpre, F->R, n, X, ldx, F->tree2,
+                                              static_cast<double*>(dV), F->ldv)));
+    }
+  } else {
+    HL("grad_leaf", (launch_grad_leaf<float>(st, F->nleaf, F->m_max, F->d_off, n, X, ldx, Lam, ldl,
+                                             static_cast<float*>(dD), F->ldd)));
+    if (F->R > 0 && L > 0) {
+      HL("grad_gen", (launch_grad_gen<float>(st, F->nleaf, L, F->d_off, F->d_rpre, F->R, n, Lam, ldl, F->tree,
+                                             static_cast<float*>(dU), F->ldu)));
+      HL("grad_gen", (launch_grad_gen<float>(st, F->nleaf, L, F->d_off, F->d_rpre, F->R, n, X, ldx, F->tree2,
+                                             static_cast<float*>(dV), F->ldv)));
+    }
+  }
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_factors_y(const hodlr_factors* F, double* Yo, int64_t ldy, void* stream) {
+  if (!F || (F->R > 0 && (!Yo || ldy < F->n))) return HODLR_ERR_ARG;
+  if (F->R == 0) return HODLR_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (F->compute == HODLR_F64)
+    HL("convert", (launch_convert<double, double>(st, F->n, F->R, static_cast<const double*>(F->Y), F->n, Yo, ldy)));
+  else
+    HL("convert", (launch_convert<double, float>(st, F->n, F->R, static_cast<const float*>(F->Y), F->n, Yo, ldy)));
+  return HODLR_OK;
+}
+
+size_t hodlr_factor_bytes(const hodlr_factors* F) { return F ? F->mem.bytes + F->ws.bytes : 0; }
+
+void hodlr_destroy(hodlr_factors* F) {
+  if (!F) return;
+  hipDeviceSynchronize();
+  F->mem.release();
+  F->ws.release();
+  delete F;
+}
+
+const char* hodlr_status_string(hodlr_status s) {
+  switch (s) {
+    case HODLR_OK: return "ok";
+    case HODLR_ERR_ARG: return "invalid argument";
+    case HODLR_ERR_ALLOC: return "device allocation failed";
+    case HODLR_ERR_HIP: return "HIP runtime error";
+    case HODLR_ERR_UNSUPPORTED: return "unsupported by this build";
+    case HODLR_ERR_SINGULAR: return "exactly singular pivot";
+    case HODLR_ERR_NOT_CONVERGED: return "iterative refinement did not converge";
+  }
+  return "unknown status";
+}
+
+void hodlr_timing_enable(int32_t enable) {
+  std::lock_guard<std::mutex> g(g_tmu);
+  if (enable) {
+    drain_records();
+    g_tot.clear();
+  }
+  g_timing = enable != 0;
+}
+
+int32_t hodlr_kernel_times(const char** names, double* total_ms, int64_t* launches, int32_t cap) {
+  std::lock_guard<std::mutex> g(g_tmu);
+  drain_records();
+  int32_t i = 0;
+  for (auto& kv : g_tot) {
+    if (i < cap) {
+      if (names) names[i] = kv.first.c_str();
+      if (total_ms) total_ms[i] = kv.second.first;
+      if (launches) launches[i] = kv.second.second;
+    }
+    ++i;
+  }
+  return i;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// Internal declarations of the HODLR library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hodlr.h"
+
+namespace hodlr {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// Rows of one tile of a level pass: a run of <= kTileRows consecutive rows
+// that lies inside one node of the pass's level.
+constexpr int kTileRows = 256;
+struct Tile {
+  int64_t row0;
+  int32_t nrows;
+  int32_t node;  // node index (0-based, left to right) at the pass's level
+};
+
+// Segment of tiles summed by the reduction kernel.
+constexpr int kSegTiles = 16;
+
+// ---------------------------------------------------------------------------
+// Small device helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T ld_as(const void* p, int64_t i);
+template <>
+__device__ __forceinline__ double ld_as<double>(const void* p, int64_t i) {
+  return static_cast<const double*>(p)[i];
+}
+template <>
+__device__ __forceinline__ float ld_as<float>(const void* p, int64_t i) {
+  return static_cast<const float*>(p)[i];
+}
+
+// XCD-aware block index remap: hardware hands consecutive workgroup ids to
+// the 8 XCDs round robin; this maps them so that consecutive *logical* ids
+// land on the same XCD (and share its L2).  Bijective for any grid size.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
+  constexpr int kX = 8;
+  int64_t per = nblocks / kX;           // full rounds
+  int64_t rem = nblocks % kX;
+  int64_t x = bid % kX, j = bid / kX;
+  if (j < per) {
+    // xcd x owns logical ids [x*per + min(x, rem) ... ) of length per + (x < rem)
+    return x * per + (x < rem ? x : rem) + j;
+  }
+  // tail round (only xcds x < rem have a block here)
+  return x * per + x + per;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files).  T = compute type (double/float),
+// S = storage type of the caller's D/U/V.
+// ---------------------------------------------------------------------------
+
+// leaf LU with partial pivoting; LU blocks col-major m_max x m_max per leaf.
+template <typename T, typename S>
+hipError_t launch_leaf_lu(hipStream_t s, int nleaf, int m_max, const int64_t* d_leaf_off, const S* D,
+                          int64_t ldd, T* lu, int32_t* piv, int32_t* perm, T* udinv,
+                          unsigned long long* info);
+
+// Leaf triangular solves on column chunks.
+// trans = 0: X(I_a, :) = U_a^{-1} L_a^{-1} P_a B(I_a, :)
+// trans = 1: X(I_a, :) = P_a^T L_a^{-T} U_a^{-T} B(I_a, :)
+// B and X may alias (same type).
+template <typename T, typename S>
+hipError_t launch_leaf_trsm(hipStream_t s, int trans, int nleaf, int m_max, const int64_t* d_leaf_off,
+                            const T* lu, const int32_t* perm, const T* udinv, const S* B, int64_t ldb,
+                            T* X, int64_t ldx, int ncols);
+
+// Fused level pass on tiles:
+//   update : Z(tile, 0:nz) -= A1(tile, 0:ka) * W_node(0:ka, 0:nz)      (if ka > 0)
+//   product: P_tile(0:kb, 0:nz) = B1(tile, 0:kb)^T * Z(tile, 0:nz)      (if kb > 0)
+// nd = tile.node >> node_shift; W for node nd starts at W + (nd >> 1) * w_pstride + (nd & 1) * ka, ld = w_ld.
+// P_tile starts at P + tile * kb * nz, col-major ld = kb.
+template <typename TZ, typename SA, typename SB>
+hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, TZ* Z, int64_t ldz, int nz,
+                             const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld,
+                             int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P);
+
+// Segment sums of tile partials: out[s] = sum of tiles [desc[s].x, desc[s].x + desc[s].y).
+template <typename T>
+hipError_t launch_segment_reduce(hipStream_t s, int nsegs, const int2* d_desc, int64_t elems, const T* P, T* out);
+
+// Coupling factor for all parents of one level (children have rank r, W has Rp columns).
+// Segments of child node c: [seg_start[c], seg_start[c+1]), each r x (Rp + r) col-major.
+template <typename T>
+hipError_t launch_couple_factor(hipStream_t s, int nparents, int r, int Rp, const T* segs,
+                                const int32_t* d_seg_start, T* Klu, int32_t* Kpiv, int32_t* Kperm, T* Kud, T* W,
+                                unsigned long long* info, int level, int L);
+
+// Coupling solve for all parents of one level: w = K^{-1} rhs (trans=0) or K^{-T} rhs.
+// rhs rows of child c come from its segments (r x nrhs each); w is 2r x nrhs per parent.
+template <typename T>
+hipError_t launch_couple_solve(hipStream_t s, int trans, int nparents, int r, int nrhs, const T* segs,
+                               const int32_t* d_seg_start, const T* Klu, const int32_t* Kperm, const T* Kud, T* w);
+
+// Pairwise tree sum out[i] = in[2i] + in[2i+1] (blocks of elems doubles).
+hipError_t launch_tree_sum(hipStream_t s, int nnodes, int64_t elems, const double* in, double* out);
+
+// Projection tree: for l = 1..L, the 2^l node sums (R x nrhs each, col-major ld R) of level l
+// start at node slot (2^l - 2); slot k begins at tree + k * R * nrhs.
+__host__ __device__ inline int64_t tree_slot(int l, int node) { return ((int64_t)1 << l) - 2 + node; }
+
+// y = op(D) x + U G per leaf (FP64 arithmetic) from the projection tree.
+template <typename S>
+hipError_t launch_matvec_apply(hipStream_t s, int trans, int nleaf, int L, const int64_t* d_leaf_off,
+                               const int32_t* d_rpre, int R, const S* D, int64_t ldd, const S* Ua, int64_t lda,
+                               const double* X, int64_t ldx, const double* tree, double* Y, int64_t ldy, int nrhs);
+
+// Gradient pieces.
+template <typename S>
+hipError_t launch_grad_leaf(hipStream_t s, int nleaf, int m_max, const int64_t* d_leaf_off, int nrhs,
+                            const double* X, int64_t ldx, const double* Lam, int64_t ldl, S* dD, int64_t ldd);
+template <typename S>
+hipError_t launch_grad_gen(hipStream_t s, int nleaf, int L, const int64_t* d_leaf_off, const int32_t* d_rpre, int R,
+                           int nrhs, const double* Left, int64_t ldl, const double* tree, S* out, int64_t ldo);
+
+// Refinement helpers (FP64).
+hipError_t launch_colnorms(hipStream_t s, int64_t n, int nrhs, const double* X, int64_t ldx, double* part,
+                           double* out2, double* outinf);
+template <typename T>
+hipError_t launch_scale_down(hipStream_t s, int64_t n, int nrhs, const double* Rr, int64_t ldr, const double* sc,
+                             T* out, int64_t ldo);
+template <typename T>
+hipError_t launch_axpy_up(hipStream_t s, int64_t n, int nrhs, const T* d, int64_t ldd, const double* sc, double* X,
+                          int64_t ldx);
+hipError_t launch_residual(hipStream_t s, int64_t n, int nrhs, const double* B, int64_t ldb, double* AX, int64_t ldax);
+template <typename T, typename S>
+hipError_t launch_convert(hipStream_t s, int64_t rows, int cols, const S* in, int64_t ldi, T* out, int64_t ldo);
+
+}  // namespace hodlr

@@ -1,0 +1,312 @@
+"""Python binding of the HODLR C ABI (``include/hodlr.h``) over torch tensors.
+
+Argument marshalling only: every step of factorization, solve, adjoint,
+matrix product and gradient runs in ``libhodlr.so``.  Tensors must live on a
+ROCm device; the library fails loudly when it is missing.
+
+Layout convention (column-major at the ABI): a torch tensor of row-major
+shape ``(k, N)`` is the N x k column-major matrix, so ``D`` is ``(m_max, N)``,
+``U``/``V`` are ``(R, N)`` and right-hand sides are ``(nrhs, N)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhodlr.so")
+
+F64, F32, BF16 = 0, 1, 2
+_DT = {"fp64": F64, "fp32": F32, "bf16": BF16}
+_STATUS = {0: "ok", -1: "invalid argument", -2: "device allocation failed", -3: "HIP runtime error",
+           -4: "unsupported by this build", 1: "exactly singular pivot",
+           2: "iterative refinement did not converge"}
+OK, ERR_SINGULAR, ERR_NOT_CONVERGED = 0, 1, 2
+
+
+class HodlrError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {_STATUS.get(status, status)} (status {status})")
+        self.status = status
+
+
+class _Matrix(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("leaf_offsets", ctypes.POINTER(ctypes.c_int64)), ("ranks", ctypes.POINTER(ctypes.c_int32)),
+                ("dtype", ctypes.c_int), ("D", ctypes.c_void_p), ("ldd", ctypes.c_int64),
+                ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64), ("V", ctypes.c_void_p), ("ldv", ctypes.c_int64)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("column", ctypes.c_int32), ("node", ctypes.c_int64)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("refine", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("relres", ctypes.c_double)]
+
+
+EXPORTS = ["hodlr_factor", "hodlr_refactor", "hodlr_solve", "hodlr_solve_adjoint", "hodlr_matvec", "hodlr_grad",
+           "hodlr_factors_y", "hodlr_factor_bytes", "hodlr_destroy", "hodlr_status_string",
+           "hodlr_timing_enable", "hodlr_kernel_times"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhodlr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2208_06290_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.hodlr_factor.argtypes = [ctypes.POINTER(_Matrix), ctypes.c_int, vp, ctypes.POINTER(vp), ctypes.POINTER(_Info)]
+    lib.hodlr_refactor.argtypes = [vp, ctypes.POINTER(_Matrix), vp, ctypes.POINTER(_Info)]
+    for f in (lib.hodlr_solve, lib.hodlr_solve_adjoint):
+        f.argtypes = [vp, i64, vp, i64, ctypes.POINTER(_Opts), vp, ctypes.POINTER(_Stats)]
+    lib.hodlr_matvec.argtypes = [ctypes.POINTER(_Matrix), i32, i64, vp, i64, vp, i64, vp]
+    lib.hodlr_grad.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp, vp, vp]
+    lib.hodlr_factors_y.argtypes = [vp, vp, i64, vp]
+    lib.hodlr_factor_bytes.argtypes = [vp]
+    lib.hodlr_factor_bytes.restype = ctypes.c_size_t
+    lib.hodlr_destroy.argtypes = [vp]
+    lib.hodlr_destroy.restype = None
+    lib.hodlr_status_string.argtypes = [ctypes.c_int]
+    lib.hodlr_status_string.restype = ctypes.c_char_p
+    lib.hodlr_timing_enable.argtypes = [i32]
+    lib.hodlr_timing_enable.restype = None
+    lib.hodlr_kernel_times.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64), i32]
+    lib.hodlr_kernel_times.restype = i32
+    for name in ("hodlr_factor", "hodlr_refactor", "hodlr_solve", "hodlr_solve_adjoint", "hodlr_matvec",
+                 "hodlr_grad", "hodlr_factors_y"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_dev(t: torch.Tensor, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+
+
+class HODLRMatrix:
+    """A HODLR matrix given by its leaf blocks and per-level generators.
+
+    D: (m_max, N) tensor (N x m_max column-major stack of leaf blocks);
+    U, V: (R, N) tensors (U_big / V_big); ranks: r_1..r_L;
+    leaf_offsets: 2**L + 1 row boundaries (None = uniform).
+    """
+
+    def __init__(self, D: torch.Tensor, U: torch.Tensor, V: torch.Tensor, ranks: Sequence[int],
+                 leaf_offsets: Optional[Sequence[int]] = None):
+        self.ranks = [int(r) for r in ranks]
+        self.levels = len(self.ranks)
+        self.n = int(D.shape[1])
+        self.D, self.U, self.V = D, U, V
+        for t, nm in ((D, "D"), (U, "U"), (V, "V")):
+            _check_dev(t, nm)
+            if t.dtype not in (torch.float64, torch.float32) or t.dtype != D.dtype:
+                raise ValueError("D, U, V must share dtype float64 or float32")
+            if t.dim() != 2 or t.shape[1] != self.n or t.stride(1) != 1:
+                raise ValueError(f"{nm} must be a (k, N) tensor with unit stride along N")
+        self.leaf_offsets = None if leaf_offsets is None else np.ascontiguousarray(leaf_offsets, dtype=np.int64)
+        self._ranks_c = (ctypes.c_int32 * max(1, self.levels))(*self.ranks)
+        self._off_c = None if self.leaf_offsets is None else self.leaf_offsets.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_int64))
+
+    @classmethod
+    def from_inputs(cls, inp) -> "HODLRMatrix":
+        return cls(inp.D, inp.U, inp.V, inp.ranks, inp.leaf_offsets)
+
+    def c_struct(self) -> _Matrix:
+        m = _Matrix()
+        m.n = self.n
+        m.levels = self.levels
+        m.leaf_offsets = self._off_c if self._off_c is not None else ctypes.POINTER(ctypes.c_int64)()
+        m.ranks = self._ranks_c
+        m.dtype = F64 if self.D.dtype == torch.float64 else F32
+        m.D, m.ldd = self.D.data_ptr(), self.D.stride(0)
+        m.U, m.ldu = self.U.data_ptr(), max(self.U.stride(0), self.n)
+        m.V, m.ldv = self.V.data_ptr(), max(self.V.stride(0), self.n)
+        return m
+
+    @property
+    def device(self):
+        return self.D.device
+
+    def matvec(self, x: torch.Tensor, trans: bool = False) -> torch.Tensor:
+        """FP64 product A x (or A^T x); x is (N,) or (nrhs, N)."""
+        lib = load_library()
+        X, vec = _as_rhs(x, self.n)
+        Y = torch.empty_like(X)
+        m = self.c_struct()
+        st = lib.hodlr_matvec(ctypes.byref(m), int(trans), X.shape[0], X.data_ptr(), self.n, Y.data_ptr(), self.n,
+                              _stream(self.device))
+        if st:
+            raise HodlrError(st, "hodlr_matvec")
+        return Y[0] if vec else Y
+
+
+def _as_rhs(b: torch.Tensor, n: int):
+    _check_dev(b, "right-hand side")
+    vec = b.dim() == 1
+    B = b.reshape(1, -1) if vec else b
+    if B.shape[-1] != n:
+        raise ValueError(f"right-hand side must have N={n} entries per column")
+    return B.to(torch.float64).contiguous().clone(), vec
+
+
+class Factors:
+    """A factorization owned by the library (freed with the object)."""
+
+    def __init__(self, A: HODLRMatrix, handle: ctypes.c_void_p, precision: str, info: Optional[dict]):
+        self.A = A
+        self._h = handle
+        self.precision = precision
+        self.info = info
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.hodlr_destroy(h)
+            self._h = None
+
+    @property
+    def nbytes(self) -> int:
+        return int(load_library().hodlr_factor_bytes(self._h))
+
+    def refactor(self, A: Optional[HODLRMatrix] = None):
+        lib = load_library()
+        A = A or self.A
+        m = A.c_struct()
+        info = _Info()
+        st = lib.hodlr_refactor(self._h, ctypes.byref(m), _stream(A.device), ctypes.byref(info))
+        if st:
+            raise HodlrError(st, "hodlr_refactor")
+        self.A = A
+
+    def _solve(self, fn, b, refine, tol, max_iter, out_stats):
+        lib = load_library()
+        X, vec = _as_rhs(b, self.A.n)
+        o = _Opts(int(refine), int(max_iter), float(tol))
+        s = _Stats()
+        st = fn(self._h, X.shape[0], X.data_ptr(), self.A.n, ctypes.byref(o), _stream(self.A.device), ctypes.byref(s))
+        if out_stats is not None:
+            out_stats.update(iters=s.iters, converged=bool(s.converged), relres=s.relres)
+        if st and not (st == ERR_NOT_CONVERGED and out_stats is not None):
+            raise HodlrError(st, fn.__name__)
+        return X[0] if vec else X
+
+    def solve(self, b: torch.Tensor, refine: bool = False, tol: float = 1e-10, max_iter: int = 30,
+              stats: Optional[dict] = None) -> torch.Tensor:
+        """x = A^{-1} b (FP64 result); b is (N,) or (nrhs, N)."""
+        return self._solve(load_library().hodlr_solve, b, refine, tol, max_iter, stats)
+
+    def solve_adjoint(self, g: torch.Tensor, refine: bool = False, tol: float = 1e-10, max_iter: int = 30,
+                      stats: Optional[dict] = None) -> torch.Tensor:
+        """lambda = A^{-T} g (FP64 result)."""
+        return self._solve(load_library().hodlr_solve_adjoint, g, refine, tol, max_iter, stats)
+
+    def y_big(self) -> torch.Tensor:
+        """Y_big as an (R, N) float64 tensor (Y_a = A_a^{-1} U_a per level)."""
+        lib = load_library()
+        R = sum(self.A.ranks)
+        Y = torch.empty(R, self.A.n, dtype=torch.float64, device=self.A.device)
+        st = lib.hodlr_factors_y(self._h, Y.data_ptr(), self.A.n, _stream(self.A.device))
+        if st:
+            raise HodlrError(st, "hodlr_factors_y")
+        return Y
+
+    def grad(self, x: torch.Tensor, lam: torch.Tensor):
+        """(dD, dU, dV) of a loss with dL/dA = -lam x^T, in the layouts and dtype of D, U, V."""
+        lib = load_library()
+        X, _ = _as_rhs(x, self.A.n)
+        Lm, _ = _as_rhs(lam, self.A.n)
+        A = self.A
+        dD = torch.zeros_like(A.D)
+        dU = torch.zeros_like(A.U)
+        dV = torch.zeros_like(A.V)
+        if dD.stride(0) != A.D.stride(0) or dU.stride(0) != max(A.U.stride(0), A.n):
+            raise ValueError("gradient buffers need the leading dimensions of D, U, V")
+        st = lib.hodlr_grad(self._h, X.shape[0], X.data_ptr(), A.n, Lm.data_ptr(), A.n, dD.data_ptr(),
+                            dU.data_ptr(), dV.data_ptr(), _stream(A.device))
+        if st:
+            raise HodlrError(st, "hodlr_grad")
+        return dD, dU, dV
+
+
+def factor(A: HODLRMatrix, precision: str = "fp64", raise_singular: bool = True) -> Factors:
+    """Factorize A (precision: 'fp64', 'fp32' or 'bf16')."""
+    lib = load_library()
+    m = A.c_struct()
+    h = ctypes.c_void_p()
+    info = _Info()
+    st = lib.hodlr_factor(ctypes.byref(m), _DT[precision], _stream(A.device), ctypes.byref(h), ctypes.byref(info))
+    if st < 0 or (st and raise_singular):
+        if h:
+            lib.hodlr_destroy(h)
+        raise HodlrError(st, "hodlr_factor") if st != ERR_SINGULAR else _singular(info)
+    inf = dict(level=info.level, column=info.column, node=info.node) if st == ERR_SINGULAR else None
+    return Factors(A, h, precision, inf)
+
+
+def _singular(info: _Info) -> HodlrError:
+    e = HodlrError(ERR_SINGULAR, f"hodlr_factor (level {info.level}, node {info.node}, column {info.column})")
+    e.info = dict(level=info.level, column=info.column, node=info.node)
+    return e
+
+
+def kernel_times(reset: bool = False) -> dict:
+    """Per-kernel {name: (total_ms, launches)} recorded with HIP events."""
+    lib = load_library()
+    cap = 64
+    names = (ctypes.c_char_p * cap)()
+    ms = (ctypes.c_double * cap)()
+    cnt = (ctypes.c_int64 * cap)()
+    k = lib.hodlr_kernel_times(names, ms, cnt, cap)
+    return {names[i].decode(): (ms[i], cnt[i]) for i in range(min(k, cap))}
+
+
+def timing(enable: bool):
+    load_library().hodlr_timing_enable(1 if enable else 0)
+
+
+class HodlrSolve(torch.autograd.Function):
+    """x = A^{-1} b with gradients for b, D, U, V (adjoint solve on the same factors).
+
+    forward(b, D, U, V, ranks, leaf_offsets, precision) -> x (float64, shape of b)
+    """
+
+    @staticmethod
+    def forward(ctx, b, D, U, V, ranks, leaf_offsets=None, precision="fp64"):
+        A = HODLRMatrix(D.detach(), U.detach(), V.detach(), ranks, leaf_offsets)
+        F = factor(A, precision)
+        x = F.solve(b.detach())
+        ctx.F = F
+        ctx.vec = b.dim() == 1
+        ctx.b_dtype = b.dtype
+        ctx.save_for_backward(x)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        F = ctx.F
+        lam = F.solve_adjoint(gx.detach())
+        dD, dU, dV = F.grad(x, lam)
+        db = lam.to(ctx.b_dtype)
+        return db, dD, dU, dV, None, None, None

@@ -1,0 +1,289 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every comparison is element by element on the same seeded inputs.  FP64 bar:
+1e-12 relative (the stated target for the FP64 path); mixed precision: the
+FP64 residual after refinement must reach 1e-10, checked on the host by the
+oracle's own matrix product."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def H_():
+    from paper_2208_06290_amd import hodlr
+    return hodlr
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _nonuniform_offsets(n, L, seed, lo=0.5, hi=1.5, min_leaf=5, max_leaf=256):
+    rng = np.random.default_rng(seed)
+    for _ in range(100):
+        w = rng.uniform(lo, hi, 1 << L)
+        sizes = np.maximum(min_leaf, np.round(w / w.sum() * n)).astype(np.int64)
+        sizes[-1] += n - sizes.sum()
+        if sizes.min() >= min_leaf and sizes.max() <= max_leaf:
+            return np.concatenate([[0], np.cumsum(sizes)])
+    raise RuntimeError("could not draw offsets")
+
+
+def _case(n, leaf, ranks, seed, offsets=None, dtype=torch.float64, shift=4.0):
+    inp = W.synthetic(n, leaf, ranks, seed=seed, leaf_offsets=offsets, dtype=dtype, shift=shift)
+    H = O.from_inputs(inp)
+    A = H_().HODLRMatrix.from_inputs(inp.to(DEV))
+    return inp, H, A
+
+
+def _rhs(n, k, seed):
+    return np.random.default_rng(seed).standard_normal((n, k))
+
+
+def _to_dev(X):  # N x k numpy -> (k, N) device tensor
+    return torch.as_tensor(np.ascontiguousarray(X.T), device=DEV)
+
+
+def _from_dev(t):  # (k, N) tensor -> N x k numpy
+    return t.detach().cpu().numpy().T
+
+
+# ---------------------------------------------------------------------------
+CASES = {
+    "L0_leaf200": dict(n=200, leaf=200, ranks=[]),
+    "L1_r10": dict(n=128, leaf=64, ranks=[10]),
+    "cfg0_like": dict(n=4096, leaf=64, ranks=16),
+    "ragged_L4": dict(n=1000, leaf=None, L=4, ranks=[7, 0, 13, 5]),
+    "ragged_L6": dict(n=3001, leaf=None, L=6, ranks=[33, 20, 64, 9, 1, 17]),
+    "leaf256_L3": dict(n=2048, leaf=256, ranks=[32, 32, 32]),
+    "leaf128_L5_r64": dict(n=4096, leaf=128, ranks=64),
+    "deep_L8": dict(n=4096, leaf=16, ranks=[4, 8, 3, 5, 6, 2, 7, 3]),
+}
+
+
+def _build(name, seed=0):
+    c = CASES[name]
+    off = _nonuniform_offsets(c["n"], c["L"], seed + 11) if c.get("leaf") is None else None
+    return _case(c["n"], c.get("leaf") or 0, c["ranks"], seed, offsets=off)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("nrhs", [1, 3, 70])
+def test_fp64_solve_matches_oracle(name, nrhs):
+    _say(f"case {name} nrhs={nrhs}")
+    inp, H, A = _build(name)
+    hd = H_()
+    B = _rhs(H.N, nrhs, 1)
+    F = hd.factor(A, "fp64")
+    X = _from_dev(F.solve(_to_dev(B)))
+    Xo = O.solve(O.factor(H), B)
+    assert _rel(X, Xo) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["cfg0_like", "ragged_L6", "leaf128_L5_r64", "deep_L8"])
+def test_Y_big_matches_oracle(name):
+    _say(f"Y case {name}")
+    inp, H, A = _build(name, seed=2)
+    F = H_().factor(A, "fp64")
+    Y = _from_dev(F.y_big())
+    Yo = O.y_big(O.factor(H))
+    for level in range(1, H.L + 1):
+        c0, c1 = H.colrange(level)
+        if c1 > c0:
+            assert _rel(Y[:, c0:c1], Yo[:, c0:c1]) < 1e-12, level
+
+
+def test_cfg0_manufactured_solution():
+    """Workload 0: b = A x_true with x_true ~ N(0,1); recover x_true."""
+    _say("cfg0 manufactured")
+    inp = W.make_config(0)
+    H = O.from_inputs(inp)
+    A = H_().HODLRMatrix.from_inputs(inp.to(DEV))
+    xt = W.gaussian_rhs(H.N, 1, seed=0).numpy().T
+    b = O.matvec(H, xt)
+    x = _from_dev(H_().factor(A).solve(_to_dev(b)))
+    assert _rel(x, np.linalg.solve(O.assemble_dense(H), b)) < 1e-12
+    assert _rel(x, xt) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["cfg0_like", "ragged_L4", "ragged_L6", "deep_L8"])
+def test_adjoint_matches_oracle(name):
+    _say(f"adjoint {name}")
+    inp, H, A = _build(name, seed=3)
+    G = _rhs(H.N, 2, 4)
+    F = H_().factor(A)
+    lam = _from_dev(F.solve_adjoint(_to_dev(G)))
+    assert _rel(lam, O.solve_adjoint(H, G)) < 1e-12
+    b = _rhs(H.N, 2, 5)
+    x = _from_dev(F.solve(_to_dev(b)))
+    assert abs(np.sum(x * G) - np.sum(b * lam)) < 1e-12 * abs(np.sum(x * G)) + 1e-12
+
+
+@pytest.mark.parametrize("name", ["cfg0_like", "ragged_L6", "L0_leaf200"])
+@pytest.mark.parametrize("trans", [False, True])
+def test_matvec_matches_oracle(name, trans):
+    _say(f"matvec {name} trans={trans}")
+    inp, H, A = _build(name, seed=4)
+    X = _rhs(H.N, 5, 6)
+    Y = _from_dev(A.matvec(_to_dev(X), trans=trans))
+    assert _rel(Y, O.matvec(H, X, trans=trans)) < 1e-13
+
+
+@pytest.mark.parametrize("name", ["cfg0_like", "ragged_L6"])
+def test_gradients_match_oracle(name):
+    _say(f"grad {name}")
+    inp, H, A = _build(name, seed=5)
+    X = _rhs(H.N, 3, 7)
+    Lam = _rhs(H.N, 3, 8)
+    F = H_().factor(A)
+    dD, dU, dV = F.grad(_to_dev(X), _to_dev(Lam))
+    rD, rU, rV = O.grad_structured(H, X, Lam)
+    dDn = dD.cpu().numpy().T
+    for i in range(1 << H.L):
+        s, e = O.node_range(H, H.L, i)
+        assert _rel(dDn[s:e, :e - s], rD[s:e, :e - s]) < 1e-13
+    assert _rel(dU.cpu().numpy().T, rU) < 1e-13
+    assert _rel(dV.cpu().numpy().T, rV) < 1e-13
+
+
+def test_autograd_function_matches_oracle():
+    _say("autograd")
+    inp, H, A = _build("ragged_L4", seed=6)
+    hd = H_()
+    b = torch.as_tensor(_rhs(H.N, 1, 9)[:, 0], device=DEV)
+    t = torch.as_tensor(_rhs(H.N, 1, 10)[:, 0], device=DEV)
+    D = inp.D.to(DEV).clone().requires_grad_(True)
+    U = inp.U.to(DEV).clone().requires_grad_(True)
+    V = inp.V.to(DEV).clone().requires_grad_(True)
+    bb = b.clone().requires_grad_(True)
+    x = hd.HodlrSolve.apply(bb, D, U, V, inp.ranks, inp.leaf_offsets)
+    loss = ((x - t) ** 2).sum()
+    loss.backward()
+    L0, xo, lam, rD, rU, rV = O.loss_and_grads(H, b.cpu().numpy(), t.cpu().numpy())
+    assert abs(loss.item() - L0) < 1e-12 * abs(L0)
+    assert _rel(bb.grad.cpu().numpy(), lam) < 1e-12
+    dDn = D.grad.cpu().numpy().T
+    for i in range(1 << H.L):
+        s, e = O.node_range(H, H.L, i)
+        assert _rel(dDn[s:e, :e - s], rD[s:e, :e - s]) < 1e-12
+    assert _rel(U.grad.cpu().numpy().T, rU) < 1e-12
+    assert _rel(V.grad.cpu().numpy().T, rV) < 1e-12
+
+
+@pytest.mark.parametrize("storage", [torch.float64, torch.float32])
+def test_fp32_factor_with_refinement(storage):
+    _say(f"fp32 factor, storage {storage}")
+    inp = W.synthetic(4096, 128, 32, seed=7, dtype=storage)
+    H = O.from_inputs(inp)
+    A = H_().HODLRMatrix.from_inputs(inp.to(DEV))
+    B = _rhs(H.N, 4, 11)
+    F = H_().factor(A, "fp32")
+    x0 = _from_dev(F.solve(_to_dev(B)))
+    Xo = O.solve(O.factor(H), B)
+    e32 = _rel(x0, Xo)
+    _say(f"  plain fp32 solve rel error {e32:.2e}")
+    assert e32 < 1e-4
+    st = {}
+    x = _from_dev(F.solve(_to_dev(B), refine=True, tol=1e-10, stats=st))
+    _say(f"  refined: {st}")
+    assert st["converged"] and st["relres"] <= 1e-10
+    assert O.relres(H, x, B) <= 1e-10
+    assert _rel(x, Xo) < 1e-9
+    lam = _from_dev(F.solve_adjoint(_to_dev(B), refine=True, tol=1e-10))
+    assert _rel(lam, O.solve_adjoint(H, B)) < 1e-9
+
+
+def test_refinement_reports_non_convergence():
+    """kappa * u_fp32 >> 1: refinement must not claim success."""
+    _say("refine non-convergence")
+    inp = W.synthetic(256, 32, 4, seed=8)
+    # columns 3 and 4 of A equal up to 1e-11 e_3: leaf 0 columns and V rows copied
+    inp.D[3, 0:32] = inp.D[4, 0:32]
+    inp.D[3, 3] += 1e-11
+    inp.V[:, 3] = inp.V[:, 4]
+    H = O.from_inputs(inp)
+    assert np.linalg.cond(O.assemble_dense(H)) > 1e9
+    A = H_().HODLRMatrix.from_inputs(inp.to(DEV))
+    F = H_().factor(A, "fp32")
+    st = {}
+    F.solve(_to_dev(_rhs(H.N, 1, 12)), refine=True, tol=1e-10, max_iter=8, stats=st)
+    _say(f"  {st}")
+    assert not st["converged"] and st["relres"] > 1e-10
+
+
+def test_singular_leaf_is_reported():
+    _say("singular leaf")
+    inp = W.synthetic(512, 64, 8, seed=9)
+    inp.D[5, 64 * 3:64 * 4] = 0.0   # leaf 3, column 5 of its block is zero
+    A = H_().HODLRMatrix.from_inputs(inp.to(DEV))
+    with pytest.raises(H_().HodlrError) as e:
+        H_().factor(A)
+    assert e.value.status == 1
+    assert e.value.info["level"] == 3 and e.value.info["node"] == 3 and e.value.info["column"] <= 5
+
+
+def test_singular_coupling_matrix_is_reported():
+    _say("singular K")
+    D = torch.ones(1, 2, dtype=torch.float64, device=DEV)
+    U = torch.ones(1, 2, dtype=torch.float64, device=DEV)
+    A = H_().HODLRMatrix(D, U, U.clone(), [1], [0, 1, 2])
+    with pytest.raises(H_().HodlrError) as e:
+        H_().factor(A)
+    assert e.value.status == 1 and e.value.info["level"] == 0
+
+
+def test_bitwise_determinism():
+    _say("determinism")
+    inp, H, A = _build("leaf256_L3", seed=10)
+    B = _to_dev(_rhs(H.N, 2, 13))
+    hd = H_()
+    F1 = hd.factor(A)
+    F2 = hd.factor(A)
+    assert torch.equal(F1.y_big(), F2.y_big())
+    assert torch.equal(F1.solve(B), F2.solve(B))
+    assert torch.equal(F1.solve_adjoint(B), F1.solve_adjoint(B))
+
+
+def test_refactor_reuses_storage():
+    _say("refactor")
+    inp, H, A = _build("cfg0_like", seed=11)
+    inp2 = W.synthetic(4096, 64, 16, seed=12)
+    hd = H_()
+    F = hd.factor(A)
+    nb = F.nbytes
+    A2 = hd.HODLRMatrix.from_inputs(inp2.to(DEV))
+    F.refactor(A2)
+    assert F.nbytes == nb
+    B = _rhs(4096, 1, 14)
+    assert _rel(_from_dev(F.solve(_to_dev(B))), O.solve(O.factor(O.from_inputs(inp2)), B)) < 1e-12
+
+
+def test_many_tiles_and_segments():
+    """N = 65536, leaf 256, r = 32: nodes of the top levels span 128 tiles,
+    so the products go through the segment reduction."""
+    _say("many tiles N=65536")
+    inp, H, A = _case(65536, 256, 32, seed=13)
+    B = _rhs(H.N, 2, 15)
+    F = H_().factor(A)
+    X = _from_dev(F.solve(_to_dev(B)))
+    assert _rel(X, O.solve(O.factor(H), B)) < 1e-12
+    G = _from_dev(F.solve_adjoint(_to_dev(B)))
+    assert O.relres(O.transpose(H), G, B) < 1e-13
