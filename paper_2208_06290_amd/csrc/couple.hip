@@ -7,9 +7,11 @@
 // segment sums of them; they are summed here in fixed order.
 //
 // couple_factor: one workgroup per parent; K is formed and LU-factored with
-//   partial pivoting in LDS (largest magnitude, lowest row on ties), then the
-//   right-hand sides [V_a^T Y_big(I_a, 1:R_l); V_b^T Y_big(I_b, 1:R_l)] are
-//   solved column group by column group (eq. "e:node1") into W.
+//   partial pivoting in LDS (largest magnitude, lowest row on ties) and the
+//   right-hand sides [V_a^T Y_big(I_a, 1:R_l); V_b^T Y_big(I_b, 1:R_l)] of
+//   eq. "e:node1" are summed into W; the MFMA block solver then overwrites W
+//   with K^{-1} W.  The LU of K is stored zero-padded to kp x kp (kp = 2r
+//   rounded up to 16) so the block solver needs no bounds checks.
 // couple_solve: one wave per parent; w = K^{-1} [V_a^T x_a; V_b^T x_b]
 //   (eq. "e:node3") or the transposed solve used by the adjoint.
 // Lanes own rows of the right-hand side (2r <= 128 -> two rows per lane) and
@@ -68,10 +70,10 @@ __device__ __forceinline__ float bcast<float>(float v, int srclane) {
 }
 
 // One wave solves K z = y for NC right-hand-side columns held as x[slot][c]
-// (row = slot * 64 + lane).  Kf: LU factor (col-major, ld n2) in LDS or global,
+// (row = slot * 64 + lane).  Kf: LU factor (col-major, leading dimension ld),
 // kud: reciprocal diagonal.  Rows >= n2 are ignored.
 template <typename T, int NC, int TRANS>
-__device__ __forceinline__ void wave_lu_solve(T (&x)[2][NC], const T* Kf, const T* kud, int n2, int lane) {
+__device__ __forceinline__ void wave_lu_solve(T (&x)[2][NC], const T* Kf, const T* kud, int n2, int ld, int lane) {
   if (!TRANS) {
     // L (unit lower) then U
     for (int j = 0; j < n2; ++j) {
@@ -83,7 +85,7 @@ __device__ __forceinline__ void wave_lu_solve(T (&x)[2][NC], const T* Kf, const 
       for (int s = 0; s < 2; ++s) {
         const int row = s * 64 + lane;
         if (row > j && row < n2) {
-          const T f = Kf[row + j * n2];
+          const T f = Kf[row + j * ld];
 #pragma unroll
           for (int c = 0; c < NC; ++c) x[s][c] -= f * xj[c];
         }
@@ -102,7 +104,7 @@ __device__ __forceinline__ void wave_lu_solve(T (&x)[2][NC], const T* Kf, const 
 #pragma unroll
           for (int c = 0; c < NC; ++c) x[s][c] = xj[c];
         } else if (row < j) {
-          const T f = Kf[row + j * n2];
+          const T f = Kf[row + j * ld];
 #pragma unroll
           for (int c = 0; c < NC; ++c) x[s][c] -= f * xj[c];
         }
@@ -123,7 +125,7 @@ __device__ __forceinline__ void wave_lu_solve(T (&x)[2][NC], const T* Kf, const 
 #pragma unroll
           for (int c = 0; c < NC; ++c) x[s][c] = xj[c];
         } else if (row > j && row < n2) {
-          const T f = Kf[j + row * n2];
+          const T f = Kf[j + row * ld];
 #pragma unroll
           for (int c = 0; c < NC; ++c) x[s][c] -= f * xj[c];
         }
@@ -138,7 +140,7 @@ __device__ __forceinline__ void wave_lu_solve(T (&x)[2][NC], const T* Kf, const 
       for (int s = 0; s < 2; ++s) {
         const int row = s * 64 + lane;
         if (row < j) {
-          const T f = Kf[j + row * n2];
+          const T f = Kf[j + row * ld];
 #pragma unroll
           for (int c = 0; c < NC; ++c) x[s][c] -= f * xj[c];
         }
@@ -151,15 +153,15 @@ __device__ __forceinline__ void wave_lu_solve(T (&x)[2][NC], const T* Kf, const 
 // couple_factor
 // ---------------------------------------------------------------------------
 constexpr int kCfThreads = 256;
-constexpr int kCfCols = 8;  // right-hand-side columns per wave and step
 
 template <typename T>
-__global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int Rp, const T* __restrict__ segs,
+__global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp, int Rp, const T* __restrict__ segs,
                                                                    const int32_t* __restrict__ seg_start,
                                                                    T* __restrict__ Klu, int32_t* __restrict__ Kpiv,
                                                                    int32_t* __restrict__ Kperm,
-                                                                   T* __restrict__ Kud, T* __restrict__ W,
-                                                                   unsigned long long* info, int level, int L) {
+                                                                   T* __restrict__ Kud, T* __restrict__ Kinv,
+                                                                   T* __restrict__ W, unsigned long long* info,
+                                                                   int level, int L) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* K = reinterpret_cast<T*>(smem_raw);  // n2 x n2, col-major
   __shared__ T redv[kCfThreads / 64];
@@ -247,9 +249,12 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int Rp
     }
     __syncthreads();
   }
-  // store the factors, the composed permutation and the reciprocal diagonal
-  T* Kg = Klu + (int64_t)g * n2 * n2;
-  for (int e = tid; e < n2 * n2; e += kCfThreads) Kg[e] = K[e];
+  // store the factors (zero-padded kp x kp), the composed permutation and the reciprocal diagonal
+  T* Kg = Klu + (int64_t)g * kp * kp;
+  for (int e = tid; e < kp * kp; e += kCfThreads) {
+    const int i = e % kp, j = e / kp;
+    Kg[e] = (i < n2 && j < n2) ? K[i + j * n2] : T(0);
+  }
   if (tid == 0) {
     for (int i = 0; i < n2; ++i) sperm[i] = i;
     for (int j = 0; j < n2; ++j) {
@@ -260,64 +265,72 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int Rp
     }
   }
   __syncthreads();
-  T* kud_s = K + n2 * n2;  // reciprocal diagonal kept in LDS for the W solve
-  for (int i = tid; i < n2; i += kCfThreads) {
-    Kpiv[(int64_t)g * n2 + i] = spiv[i];
-    Kperm[(int64_t)g * n2 + i] = sperm[i];
-    const T d = T(1) / K[i + i * n2];
-    Kud[(int64_t)g * n2 + i] = d;
-    kud_s[i] = d;
+  for (int i = tid; i < kp; i += kCfThreads) {
+    Kpiv[(int64_t)g * kp + i] = i < n2 ? spiv[i] : i;
+    Kperm[(int64_t)g * kp + i] = i < n2 ? sperm[i] : i;
+    Kud[(int64_t)g * kp + i] = i < n2 ? T(1) / K[i + i * n2] : T(1);
   }
-  __syncthreads();
-  if (Rp == 0) return;
-  // W = K^{-1} [V_a^T Y(I_a, 0:Rp); V_b^T Y(I_b, 0:Rp)], column groups per wave
-  T* Wg = W + (int64_t)g * n2 * Rp;
-  const int ngroups = (Rp + kCfCols - 1) / kCfCols;
-  for (int grp = wid; grp < ngroups; grp += kCfThreads / 64) {
-    const int cbase = grp * kCfCols;
-    T x[2][kCfCols];
+  // inverses of the 16 x 16 diagonal blocks of L and U (padded part: identity) for the block solver
+  {
+    const int nbd = kp >> 4;
+    const int which = tid >> 7;  // 0: L, 1: U
+    const int kb = (tid >> 4) & 7, cc = tid & 15;
+    if (kb < nbd) {
+      const int g0 = 16 * kb;
+      auto Kel = [&](int i, int j) -> T { return (i < n2 && j < n2) ? K[i + j * n2] : T(0); };
+      T x[16];
+      if (which == 0) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int row = s * 64 + lane;
+        for (int i = 0; i < 16; ++i) {
+          T sv = (i == cc) ? T(1) : T(0);
 #pragma unroll
-      for (int c = 0; c < kCfCols; ++c) {
-        T v = T(0);
-        if (row < n2 && cbase + c < Rp) {
-          const int src = sperm[row];
-          const int node = src < r ? a : b;
-          v = seg_sum(segs, seg_start, node, elems, (src % r) + (int64_t)(cbase + c) * r);
+          for (int jj = 0; jj < i; ++jj) sv -= Kel(g0 + i, g0 + jj) * x[jj];
+          x[i] = (i >= cc) ? sv : T(0);
         }
-        x[s][c] = v;
+      } else {
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+          T sv = (i == cc) ? T(1) : T(0);
+#pragma unroll
+          for (int jj = i + 1; jj < 16; ++jj) sv -= Kel(g0 + i, g0 + jj) * x[jj];
+          const T d = (g0 + i < n2) ? K[(g0 + i) * (n2 + 1)] : T(1);
+          x[i] = (i <= cc) ? sv / d : T(0);
+        }
       }
-    }
-    wave_lu_solve<T, kCfCols, 0>(x, K, kud_s, n2, lane);
+      T* dst = Kinv + ((int64_t)g * 2 + which) * nbd * 256 + kb * 256;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int row = s * 64 + lane;
-#pragma unroll
-      for (int c = 0; c < kCfCols; ++c)
-        if (row < n2 && cbase + c < Rp) Wg[row + (int64_t)(cbase + c) * n2] = x[s][c];
+      for (int i = 0; i < 16; ++i) dst[i * 16 + cc] = x[i];
     }
+  }
+  // right-hand sides of eq. "e:node1", unpermuted (the block solver applies the pivots)
+  T* Wg = W + (int64_t)g * n2 * Rp;
+  for (int64_t e = tid; e < (int64_t)n2 * Rp; e += kCfThreads) {
+    const int i = (int)(e % n2), cc = (int)(e / n2);
+    const int node = i < r ? a : b;
+    Wg[e] = seg_sum(segs, seg_start, node, elems, (i % r) + (int64_t)cc * r);
   }
 }
 
 template <typename T>
-hipError_t launch_couple_factor(hipStream_t s, int nparents, int r, int Rp, const T* segs,
-                                const int32_t* d_seg_start, T* Klu, int32_t* Kpiv, int32_t* Kperm, T* Kud, T* W,
-                                unsigned long long* info, int level, int L) {
+hipError_t launch_couple_factor(hipStream_t s, int nparents, int r, int kp, int Rp, const T* segs,
+                                const int32_t* d_seg_start, T* Klu, int32_t* Kpiv, int32_t* Kperm, T* Kud, T* Kinv,
+                                T* W, unsigned long long* info, int level, int L) {
   if (nparents == 0 || r == 0) return hipSuccess;
-  const size_t smem = sizeof(T) * ((size_t)4 * r * r + 2 * r);
+  if (kp > 128) return hipErrorInvalidValue;
+  const size_t smem = sizeof(T) * (size_t)4 * r * r;
   auto k = couple_factor_kernel<T>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(nparents), dim3(kCfThreads), smem, s, r, Rp, segs, d_seg_start, Klu, Kpiv, Kperm, Kud,
-                     W, info, level, L);
+  hipLaunchKernelGGL(k, dim3(nparents), dim3(kCfThreads), smem, s, r, kp, Rp, segs, d_seg_start, Klu, Kpiv, Kperm,
+                     Kud, Kinv, W, info, level, L);
   return hipGetLastError();
 }
-template hipError_t launch_couple_factor<double>(hipStream_t, int, int, int, const double*, const int32_t*, double*,
-                                                 int32_t*, int32_t*, double*, double*, unsigned long long*, int, int);
-template hipError_t launch_couple_factor<float>(hipStream_t, int, int, int, const float*, const int32_t*, float*,
-                                                int32_t*, int32_t*, float*, float*, unsigned long long*, int, int);
+template hipError_t launch_couple_factor<double>(hipStream_t, int, int, int, int, const double*, const int32_t*,
+                                                 double*, int32_t*, int32_t*, double*, double*, double*,
+                                                 unsigned long long*, int, int);
+template hipError_t launch_couple_factor<float>(hipStream_t, int, int, int, int, const float*, const int32_t*,
+                                                float*, int32_t*, int32_t*, float*, float*, float*,
+                                                unsigned long long*, int, int);
 
 // ---------------------------------------------------------------------------
 // couple_solve: one wave per parent, columns in groups of kCsCols
@@ -325,7 +338,7 @@ template hipError_t launch_couple_factor<float>(hipStream_t, int, int, int, cons
 constexpr int kCsCols = 4;
 
 template <typename T, int TRANS>
-__global__ __launch_bounds__(64) void couple_solve_kernel(int r, int nrhs, const T* __restrict__ segs,
+__global__ __launch_bounds__(64) void couple_solve_kernel(int r, int kp, int nrhs, const T* __restrict__ segs,
                                                           const int32_t* __restrict__ seg_start,
                                                           const T* __restrict__ Klu, const int32_t* __restrict__ Kperm,
                                                           const T* __restrict__ Kud, T* __restrict__ w) {
@@ -334,9 +347,9 @@ __global__ __launch_bounds__(64) void couple_solve_kernel(int r, int nrhs, const
   const int n2 = 2 * r;
   const int lane = threadIdx.x;
   const int64_t elems = (int64_t)r * nrhs;
-  const T* Kf = Klu + (int64_t)g * n2 * n2;
-  const int32_t* pm = Kperm + (int64_t)g * n2;
-  const T* kud = Kud + (int64_t)g * n2;
+  const T* Kf = Klu + (int64_t)g * kp * kp;
+  const int32_t* pm = Kperm + (int64_t)g * kp;
+  const T* kud = Kud + (int64_t)g * kp;
   T* wg = w + (int64_t)g * n2 * nrhs;
   for (int cbase = 0; cbase < nrhs; cbase += kCsCols) {
     T x[2][kCsCols];
@@ -354,7 +367,7 @@ __global__ __launch_bounds__(64) void couple_solve_kernel(int r, int nrhs, const
         x[s][c] = v;
       }
     }
-    wave_lu_solve<T, kCsCols, TRANS>(x, Kf, kud, n2, lane);
+    wave_lu_solve<T, kCsCols, TRANS>(x, Kf, kud, n2, kp, lane);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int row = s * 64 + lane;
@@ -369,20 +382,20 @@ __global__ __launch_bounds__(64) void couple_solve_kernel(int r, int nrhs, const
 }
 
 template <typename T>
-hipError_t launch_couple_solve(hipStream_t s, int trans, int nparents, int r, int nrhs, const T* segs,
+hipError_t launch_couple_solve(hipStream_t s, int trans, int nparents, int r, int kp, int nrhs, const T* segs,
                                const int32_t* d_seg_start, const T* Klu, const int32_t* Kperm, const T* Kud, T* w) {
   if (nparents == 0 || r == 0 || nrhs == 0) return hipSuccess;
   if (trans)
-    hipLaunchKernelGGL((couple_solve_kernel<T, 1>), dim3(nparents), dim3(64), 0, s, r, nrhs, segs, d_seg_start,
+    hipLaunchKernelGGL((couple_solve_kernel<T, 1>), dim3(nparents), dim3(64), 0, s, r, kp, nrhs, segs, d_seg_start,
                        Klu, Kperm, Kud, w);
   else
-    hipLaunchKernelGGL((couple_solve_kernel<T, 0>), dim3(nparents), dim3(64), 0, s, r, nrhs, segs, d_seg_start,
+    hipLaunchKernelGGL((couple_solve_kernel<T, 0>), dim3(nparents), dim3(64), 0, s, r, kp, nrhs, segs, d_seg_start,
                        Klu, Kperm, Kud, w);
   return hipGetLastError();
 }
-template hipError_t launch_couple_solve<double>(hipStream_t, int, int, int, int, const double*, const int32_t*,
+template hipError_t launch_couple_solve<double>(hipStream_t, int, int, int, int, int, const double*, const int32_t*,
                                                 const double*, const int32_t*, const double*, double*);
-template hipError_t launch_couple_solve<float>(hipStream_t, int, int, int, int, const float*, const int32_t*,
+template hipError_t launch_couple_solve<float>(hipStream_t, int, int, int, int, int, const float*, const int32_t*,
                                                const float*, const int32_t*, const float*, float*);
 
 }  // namespace hodlr

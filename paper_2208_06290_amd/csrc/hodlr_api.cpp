@@ -161,12 +161,14 @@ struct hodlr_factors {
   int32_t* piv = nullptr;
   int32_t* perm = nullptr;
   void* udinv = nullptr;
+  void* invl = nullptr;  // leaf LU scratch: inverted diagonal blocks of L
   void* Y = nullptr;
-  std::vector<int64_t> koff, kvoff;  // per parent level p: element offsets of K blocks / K vectors
+  std::vector<int64_t> koff, kvoff, kioff;  // per parent level p: offsets of K blocks / K vectors / K inverses
   void* Klu = nullptr;
   int32_t* Kpiv = nullptr;
   int32_t* Kperm = nullptr;
   void* Kud = nullptr;
+  void* Kinv = nullptr;  // inverted 16 x 16 diagonal blocks of the K factors
   // factor workspace
   void* W = nullptr;
   void* P = nullptr;
@@ -308,6 +310,9 @@ hodlr_status plan(hodlr_factors* F) {
 
 size_t tsz(hodlr_dtype c) { return c == HODLR_F64 ? 8 : 4; }
 
+// leading dimension of a stored K factor: 2r rounded up to 16
+int kpad(int r) { return (2 * r + 15) & ~15; }
+
 hodlr_status allocate_factors(hodlr_factors* F) {
   DevMem& M = F->mem;
   const int L = F->L;
@@ -327,22 +332,29 @@ hodlr_status allocate_factors(hodlr_factors* F) {
   if ((s = M.alloc(&F->perm, nl * mm))) return s;
   if ((s = M.alloc(&b, nl * mm * ts))) return s;
   F->udinv = b;
+  if ((s = M.alloc(&b, nl * 2 * (mm / 16) * 256 * ts))) return s;
+  F->invl = b;
   if ((s = M.alloc(&b, (size_t)F->n * F->R * ts))) return s;
   F->Y = b;
   F->koff.assign(L + 1, 0);
   F->kvoff.assign(L + 1, 0);
-  int64_t kk = 0, kv = 0;
+  F->kioff.assign(L + 1, 0);
+  int64_t kk = 0, kv = 0, ki = 0;
   size_t wmax = 0, pmax = 0, segmax = 0;
   for (int p = 0; p < L; ++p) {
     const int r = F->ranks[p];  // r_{p+1}
+    const int kp = kpad(r);
     F->koff[p] = kk;
     F->kvoff[p] = kv;
-    kk += (int64_t(1) << p) * 4 * r * r;
-    kv += (int64_t(1) << p) * 2 * r;
+    F->kioff[p] = ki;
+    kk += (int64_t(1) << p) * kp * kp;
+    kv += (int64_t(1) << p) * kp;
+    ki += (int64_t(1) << p) * 2 * (kp / 16) * 256;
     wmax = std::max(wmax, (size_t)(int64_t(1) << p) * 2 * r * F->Rp[p]);
   }
   F->koff[L] = kk;
   F->kvoff[L] = kv;
+  F->kioff[L] = ki;
   for (int p = 1; p <= L; ++p) {
     const int q = fwd_prod_tiles(F, p);
     const size_t elems = (size_t)F->ranks[p - 1] * F->Rp[p];
@@ -356,6 +368,8 @@ hodlr_status allocate_factors(hodlr_factors* F) {
   if ((s = M.alloc(&F->Kperm, (size_t)kv))) return s;
   if ((s = M.alloc(&b, (size_t)kv * ts))) return s;
   F->Kud = b;
+  if ((s = M.alloc(&b, (size_t)ki * ts))) return s;
+  F->Kinv = b;
   if ((s = M.alloc(&b, wmax * ts))) return s;
   F->W = b;
   if ((s = M.alloc(&b, pmax * ts))) return s;
@@ -396,10 +410,10 @@ hodlr_status run_factor(hodlr_factors* F, hipStream_t st) {
   const S* V = static_cast<const S*>(F->V);
   if (hipMemsetAsync(F->d_info, 0xFF, 2 * sizeof(unsigned long long), st) != hipSuccess) return HODLR_ERR_HIP;
   HL("leaf_lu", (launch_leaf_lu<T, S>(st, F->nleaf, F->ldl, F->d_off, D, F->ldd, tp<T>(F->lu), F->piv, F->perm,
-                                      tp<T>(F->udinv), F->d_info)));
+                                      tp<T>(F->udinv), tp<T>(F->invl), F->d_info)));
   if (F->R > 0)
     HL("leaf_trsm", (launch_leaf_trsm<T, S>(st, 0, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->perm,
-                                            tp<T>(F->udinv), U, F->ldu, Y, N, F->R)));
+                                            tp<T>(F->invl), U, F->ldu, Y, N, F->R)));
   if (L > 0) {
     // products V^T Y for the children of level L-1 (the leaves)
     HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], Y, N, F->R, (const T*)nullptr, N, 0,
@@ -414,9 +428,15 @@ hodlr_status run_factor(hodlr_factors* F, hipStream_t st) {
       hodlr_status s = prod_segments<T>(F, st, fwd_prod_tiles(F, q), q, (int64_t)r * F->Rp[q], tp<T>(F->P),
                                         tp<T>(F->segbuf), &segs, &seg_start);
       if (s) return s;
-      HL("couple_factor", (launch_couple_factor<T>(st, 1 << p, r, Rp, segs, seg_start, tp<T>(F->Klu) + F->koff[p],
-                                                   F->Kpiv + F->kvoff[p], F->Kperm + F->kvoff[p],
-                                                   tp<T>(F->Kud) + F->kvoff[p], tp<T>(F->W), F->d_info + 1, p, L)));
+      const int kp = kpad(r);
+      HL("couple_factor", (launch_couple_factor<T>(st, 1 << p, r, kp, Rp, segs, seg_start,
+                                                   tp<T>(F->Klu) + F->koff[p], F->Kpiv + F->kvoff[p],
+                                                   F->Kperm + F->kvoff[p], tp<T>(F->Kud) + F->kvoff[p],
+                                                   tp<T>(F->Kinv) + F->kioff[p], tp<T>(F->W), F->d_info + 1, p, L)));
+      if (Rp > 0 && r > 0)
+        HL("couple_trsm", (launch_block_trsm<T>(st, 0, 1 << p, kp, 2 * r, (int64_t)2 * r * Rp,
+                                                tp<T>(F->Klu) + F->koff[p], F->Kperm + F->kvoff[p],
+                                                tp<T>(F->Kinv) + F->kioff[p], tp<T>(F->W), 2 * r, Rp)));
       if (p > 0 && r > 0) {
         HL("level_pass",
            (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], Y, N, Rp, Y + (int64_t)Rp * N, N, r,
@@ -518,7 +538,7 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
   T* w = tp<T>(F->sw);
   if (!trans) {
     HL("leaf_solve", (launch_leaf_trsm<T, T>(st, 0, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->perm,
-                                             tp<T>(F->udinv), X, ldx, X, ldx, nrhs)));
+                                             tp<T>(F->invl), X, ldx, X, ldx, nrhs)));
     if (L == 0) return HODLR_OK;
     HL("solve_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], X, ldx, nrhs, (const T*)nullptr, N,
                                                  0, (const T*)nullptr, 0, 0, 0, V + (int64_t)F->Rp[L - 1] * F->ldv,
@@ -532,7 +552,7 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
         hodlr_status s = prod_segments<T>(F, st, fwd_prod_tiles(F, q), q, (int64_t)r * nrhs, P, tp<T>(F->sseg),
                                           &segs, &seg_start);
         if (s) return s;
-        HL("couple_solve", (launch_couple_solve<T>(st, 0, 1 << p, r, nrhs, segs, seg_start,
+        HL("couple_solve", (launch_couple_solve<T>(st, 0, 1 << p, r, kpad(r), nrhs, segs, seg_start,
                                                    tp<T>(F->Klu) + F->koff[p], F->Kperm + F->kvoff[p],
                                                    tp<T>(F->Kud) + F->kvoff[p], w)));
       }
@@ -558,7 +578,7 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
         hodlr_status s = prod_segments<T>(F, st, adj_prod_tiles(F, q), q, (int64_t)r * nrhs, P, tp<T>(F->sseg),
                                           &segs, &seg_start);
         if (s) return s;
-        HL("couple_solve_t", (launch_couple_solve<T>(st, 1, 1 << p, r, nrhs, segs, seg_start,
+        HL("couple_solve_t", (launch_couple_solve<T>(st, 1, 1 << p, r, kpad(r), nrhs, segs, seg_start,
                                                      tp<T>(F->Klu) + F->koff[p], F->Kperm + F->kvoff[p],
                                                      tp<T>(F->Kud) + F->kvoff[p], w)));
       }
@@ -572,7 +592,7 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
     }
   }
   HL("leaf_solve_t", (launch_leaf_trsm<T, T>(st, 1, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->perm,
-                                             tp<T>(F->udinv), X, ldx, X, ldx, nrhs)));
+                                             tp<T>(F->invl), X, ldx, X, ldx, nrhs)));
   return HODLR_OK;
 }
 

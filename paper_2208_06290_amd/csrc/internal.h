@@ -58,20 +58,26 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
 // S = storage type of the caller's D/U/V.
 // ---------------------------------------------------------------------------
 
-// leaf LU with partial pivoting; LU blocks col-major m_max x m_max per leaf.
+// leaf LU with partial pivoting; LU blocks col-major ldl x ldl per leaf (ldl % 16 == 0),
+// invl: scratch for the inverted 16 x 16 unit-lower diagonal blocks (ldl/16 x 256 per leaf).
 template <typename T, typename S>
-hipError_t launch_leaf_lu(hipStream_t s, int nleaf, int m_max, const int64_t* d_leaf_off, const S* D,
-                          int64_t ldd, T* lu, int32_t* piv, int32_t* perm, T* udinv,
-                          unsigned long long* info);
+hipError_t launch_leaf_lu(hipStream_t s, int nleaf, int ldl, const int64_t* d_leaf_off, const S* D, int64_t ldd,
+                          T* lu, int32_t* piv, int32_t* perm, T* udinv, T* invl, unsigned long long* info);
 
 // Leaf triangular solves on column chunks.
-// trans = 0: X(I_a, :) = U_a^{-1} L_a^{-1} P_a B(I_a, :)
-// trans = 1: X(I_a, :) = P_a^T L_a^{-T} U_a^{-T} B(I_a, :)
+// trans = 0: X(I_a, :) = U_a^{-1} L_a^{-1} P_a^T B(I_a, :)
+// trans = 1: X(I_a, :) = P_a L_a^{-T} U_a^{-T} B(I_a, :)
 // B and X may alias (same type).
+// dinv: per block 2 x (ldl/16) inverted 16 x 16 diagonal blocks ([0]: L, [1]: U) from the factorization.
 template <typename T, typename S>
-hipError_t launch_leaf_trsm(hipStream_t s, int trans, int nleaf, int m_max, const int64_t* d_leaf_off,
-                            const T* lu, const int32_t* perm, const T* udinv, const S* B, int64_t ldb,
-                            T* X, int64_t ldx, int ncols);
+hipError_t launch_leaf_trsm(hipStream_t s, int trans, int nleaf, int ldl, const int64_t* d_leaf_off, const T* lu,
+                            const int32_t* perm, const T* dinv, const S* B, int64_t ldb, T* X, int64_t ldx,
+                            int ncols);
+
+// The same solves for nblk equal blocks of m rows (m <= ldl): block g's rows start at X + g * ostride.
+template <typename T>
+hipError_t launch_block_trsm(hipStream_t s, int trans, int nblk, int ldl, int m, int64_t ostride, const T* lu,
+                             const int32_t* perm, const T* dinv, T* X, int64_t ldx, int ncols);
 
 // Fused level pass on tiles:
 //   update : Z(tile, 0:nz) -= A1(tile, 0:ka) * W_node(0:ka, 0:nz)      (if ka > 0)
@@ -87,17 +93,18 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, TZ* Z
 template <typename T>
 hipError_t launch_segment_reduce(hipStream_t s, int nsegs, const int2* d_desc, int64_t elems, const T* P, T* out);
 
-// Coupling factor for all parents of one level (children have rank r, W has Rp columns).
+// Coupling factor for all parents of one level (children have rank r, W has Rp columns);
+// K factors stored kp x kp (kp = 2r rounded up to 16), W gets the unsolved right-hand sides.
 // Segments of child node c: [seg_start[c], seg_start[c+1]), each r x (Rp + r) col-major.
 template <typename T>
-hipError_t launch_couple_factor(hipStream_t s, int nparents, int r, int Rp, const T* segs,
-                                const int32_t* d_seg_start, T* Klu, int32_t* Kpiv, int32_t* Kperm, T* Kud, T* W,
-                                unsigned long long* info, int level, int L);
+hipError_t launch_couple_factor(hipStream_t s, int nparents, int r, int kp, int Rp, const T* segs,
+                                const int32_t* d_seg_start, T* Klu, int32_t* Kpiv, int32_t* Kperm, T* Kud, T* Kinv,
+                                T* W, unsigned long long* info, int level, int L);
 
 // Coupling solve for all parents of one level: w = K^{-1} rhs (trans=0) or K^{-T} rhs.
 // rhs rows of child c come from its segments (r x nrhs each); w is 2r x nrhs per parent.
 template <typename T>
-hipError_t launch_couple_solve(hipStream_t s, int trans, int nparents, int r, int nrhs, const T* segs,
+hipError_t launch_couple_solve(hipStream_t s, int trans, int nparents, int r, int kp, int nrhs, const T* segs,
                                const int32_t* d_seg_start, const T* Klu, const int32_t* Kperm, const T* Kud, T* w);
 
 // Pairwise tree sum out[i] = in[2i] + in[2i+1] (blocks of elems doubles).

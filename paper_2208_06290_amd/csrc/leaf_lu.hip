@@ -1,251 +1,303 @@
 // Batched LU with partial pivoting of the leaf diagonal blocks
 // (Alg. "a:fact" leaf loop / Alg. "a:gpuf" batched_LU_factorize_inplace on D_big^L).
 //
-// One workgroup (256 threads) per leaf.  Right-looking blocked LU with panels
-// of kNB columns: the panel is factored in LDS (pivot = largest magnitude,
-// lowest row on ties, as LAPACK's idamax), row interchanges are applied to the
-// rest of the block, U12 = L11^{-1} A12 is solved per column and the trailing
-// block is updated from LDS-resident L21 / U12 with 4x4 register tiles.
+// One workgroup (256 threads = 4 waves) per leaf, left-looking by 32-column
+// chunks:
+//   1. the chunk's original columns are loaded into MFMA accumulators in the
+//      current row order (wave w owns the 16-row blocks b with b % 4 == w);
+//   2. the chunk is swept with the L blocks of all earlier chunks on MFMA
+//      (X_k = inv(L_kk) B_k by the owning wave, published through LDS,
+//      B_b -= L_bk X_k by every wave), which leaves the U rows above the panel
+//      and the Schur-complemented panel below;
+//   3. the panel (rows below, 32 columns) is factored with one thread per row,
+//      the row held in registers: pivot = largest magnitude, lowest current
+//      position on ties (LAPACK idamax), rows are not moved - each thread
+//      tracks its position, the winner broadcasts its row through LDS, two
+//      barriers per column.
+// Entries are stored by original row while factoring (later interchanges move
+// no data); a final pass writes them in pivoted order.
 //
-// Output per leaf a (block of ldl x ldl, column-major, ld = ldl; ldl = m_max rounded up to 16):
+// Output per leaf a (block of ldl x ldl, column-major, ld = ldl; ldl = m_max
+// rounded up to 16):
 //   lu     unit-lower L below the diagonal, U on and above; zero outside m_a x m_a
-//          (the padding lets the 16-row block solves run without bounds checks)
 //   piv    LAPACK-style interchanges: row j was swapped with piv[j] (0-based, >= j)
 //   perm   composed row order: row i of P^T A is row perm[i] of A
 //   udinv  1 / U_jj (1 outside m_a)
+//   inv    inverses of the 16 x 16 diagonal blocks: [0][kb] = inv(L_kb,kb) (unit
+//          lower), [1][kb] = inv(U_kb,kb) (upper); padded rows act as identity
 // First exactly-zero pivot -> atomicMin(info, leaf << 20 | column).
-#include "internal.h"
+#include "mfma.h"
 
 namespace hodlr {
 
-constexpr int kNB = 32;
 constexpr int kLuThreads = 256;
-
-template <typename T>
-__device__ __forceinline__ void argmax_abs_wave(T& v, int& i) {
-  // max |value|, lowest index on ties, across the 64 lanes of a wave
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    T ov = __shfl_xor(v, off, 64);
-    int oi = __shfl_xor(i, off, 64);
-    if (ov > v || (ov == v && oi < i)) {
-      v = ov;
-      i = oi;
-    }
-  }
-}
+constexpr int kCW = 32;  // chunk (panel) width
 
 template <typename T, typename S>
-__global__ __launch_bounds__(kLuThreads) void leaf_lu_kernel(int m_max, const int64_t* __restrict__ leaf_off,
-                                                             const S* __restrict__ D, int64_t ldd,
-                                                             T* __restrict__ lu, int32_t* __restrict__ piv,
-                                                             int32_t* __restrict__ perm, T* __restrict__ udinv,
+__global__ __launch_bounds__(kLuThreads) void leaf_lu_kernel(int ldl, const int64_t* __restrict__ leaf_off,
+                                                             const S* __restrict__ D, int64_t ldd, T* lu,
+                                                             int32_t* __restrict__ piv, int32_t* __restrict__ perm,
+                                                             T* __restrict__ udinv, T* invl,
                                                              unsigned long long* info) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* Ps = reinterpret_cast<T*>(smem_raw);                 // panel: rows 0..pr-1, ld = kLeafLd
-  constexpr int kLeafLd = HODLR_MAX_LEAF;
-  T* Us = Ps + kLeafLd * kNB;                             // U12 block: kNB x (<= 256), row-major ld 256
-  __shared__ T redv[kLuThreads / 64];
-  __shared__ int redi[kLuThreads / 64];
-  __shared__ int spiv[kNB];
-  __shared__ T spivval;
+  using M = Mfma<T>;
+  using V = typename M::V;
+  __shared__ T stage[256 * kCW];  // panel rows, row-major [row][32]
+  __shared__ T xk[2][16 * kCW];   // published X_k [row][col]
+  __shared__ T urow[2][kCW];      // pivot row of the current column
+  __shared__ int pm[256];         // position -> original (leaf-local) row
+  __shared__ T redv[4];
+  __shared__ int redk[4], redt[4];
+  __shared__ int sppos[2], spt[2];
 
   const int a = blockIdx.x;
   const int64_t o = leaf_off[a];
   const int m = (int)(leaf_off[a + 1] - o);
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wid = tid >> 6;
-  T* A = lu + (int64_t)a * m_max * m_max;
-  int32_t* pv = piv + (int64_t)a * m_max;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lq = lane >> 4;
+  T* F = lu + (int64_t)a * ldl * ldl;  // by original row while factoring
+  T* IL = invl + (int64_t)a * 2 * (ldl / 16) * 256;
+  int32_t* pv = piv + (int64_t)a * ldl;
+  const int nbk = (m + 15) >> 4;
+  const int nch = (m + kCW - 1) / kCW;
 
-  // copy D_a into the factor block, zero padding outside m x m
-  for (int64_t e = tid; e < (int64_t)m_max * m_max; e += kLuThreads) {
-    int i = (int)(e % m_max), j = (int)(e / m_max);
-    A[e] = (i < m && j < m) ? (T)D[o + i + (int64_t)j * ldd] : T(0);
+  for (int i = tid; i < 256; i += kLuThreads) pm[i] = i;
+  // zero padding outside m x m (never touched by the factorization)
+  for (int64_t e = tid; e < (int64_t)ldl * ldl; e += kLuThreads) {
+    const int i = (int)(e % ldl), j = (int)(e / ldl);
+    if (i >= m || j >= m) F[e] = T(0);
   }
   __syncthreads();
 
-  for (int k0 = 0; k0 < m; k0 += kNB) {
-    const int nb = min(kNB, m - k0);
-    const int pr = m - k0;  // panel rows
-    for (int e = tid; e < pr * nb; e += kLuThreads) {
-      int i = e % pr, j = e / pr;
-      Ps[i + j * kLeafLd] = A[(k0 + i) + (int64_t)(k0 + j) * m_max];
-    }
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-      // pivot search in column j, rows j..pr-1 (one candidate per thread)
-      T best = T(-1);
-      int bi = 0x7fffffff;
-      for (int i = j + tid; i < pr; i += kLuThreads) {
-        T v = fabs(Ps[i + j * kLeafLd]);
-        if (v > best || (v == best && i < bi)) {
-          best = v;
-          bi = i;
+  for (int c = 0; c < nch; ++c) {
+    const int c0 = kCW * c;
+    const int cw = min(kCW, m - c0);
+    // 1. load the chunk in the current row order
+    V acc[4][2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int row = 16 * (4 * q + w) + M::crow(lq, t);
+          const int col = 16 * cb + li;
+          acc[q][cb][t] = (row < m && col < cw) ? (T)D[o + pm[row] + (int64_t)(c0 + col) * ldd] : T(0);
         }
+    // 2. sweep with the L blocks of the earlier chunks
+    const int nk = 2 * c;
+    for (int k = 0; k < nk; ++k) {
+      T* xb = xk[k & 1];
+      if ((k & 3) == w) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (4 * q + w == k) {
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+              V nv = vzero<V>();
+#pragma unroll
+              for (int t = 0; t < 4; ++t) nv = M::mma(IL[k * 256 + li * 16 + M::crow(lq, t)], acc[q][cb][t], nv);
+              acc[q][cb] = nv;
+#pragma unroll
+              for (int t = 0; t < 4; ++t) xb[M::crow(lq, t) * kCW + 16 * cb + li] = nv[t];
+            }
+          }
       }
-      argmax_abs_wave(best, bi);
-      if (lane == 0) {
-        redv[wid] = best;
-        redi[wid] = bi;
+      // operands of this step's update are independent of X_k: load them before the barrier
+      T av[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int b = 4 * q + w;
+        const int prow = pm[min(16 * b + li, 255)];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+          av[q][ks] = (b > k && b < nbk) ? -F[prow + (int64_t)(16 * k + 4 * ks + lq) * ldl] : T(0);
       }
       __syncthreads();
-      if (tid == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int b = 4 * q + w;
+        if (b > k && b < nbk) {
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+              acc[q][cb] = M::mma(av[q][ks], xb[(4 * ks + lq) * kCW + 16 * cb + li], acc[q][cb]);
+        }
+      }
+    }
+    // U rows above the panel are final; panel rows go to LDS
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int row = 16 * (4 * q + w) + M::crow(lq, t);
+          const int col = 16 * cb + li;
+          if (row < m) {
+            if (row < c0) {
+              if (col < cw) F[pm[row] + (int64_t)(c0 + col) * ldl] = acc[q][cb][t];
+            } else {
+              stage[(row - c0) * kCW + col] = acc[q][cb][t];
+            }
+          }
+        }
+    __syncthreads();
+    // 3. panel factorization, one thread per panel row
+    const int pr = m - c0;
+    const bool own = tid < pr;
+    int mypos = tid;
+    bool done = false;
+    const int orig = own ? pm[c0 + tid] : 0;
+    T r[kCW];
+#pragma unroll
+    for (int cc = 0; cc < kCW; ++cc) r[cc] = own ? stage[tid * kCW + cc] : T(0);
+#pragma unroll
+    for (int j = 0; j < kCW; ++j) {
+      if (j < cw) {
+        const bool cand = own && !done;
+        T v = cand ? fabs(r[j]) : T(-1);
+        if (cand && !(v == v)) v = T(INFINITY);  // a NaN can still be chosen
+        int key = cand ? mypos : 0x7fffffff;
+        int who = tid;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const T ov = __shfl_xor(v, off, 64);
+          const int ok = __shfl_xor(key, off, 64);
+          const int ow = __shfl_xor(who, off, 64);
+          if (ov > v || (ov == v && ok < key)) {
+            v = ov;
+            key = ok;
+            who = ow;
+          }
+        }
+        if (lane == 0) {
+          redv[w] = v;
+          redk[w] = key;
+          redt[w] = who;
+        }
+        __syncthreads();
         T bv = redv[0];
-        int bx = redi[0];
-        for (int w = 1; w < kLuThreads / 64; ++w)
-          if (redv[w] > bv || (redv[w] == bv && redi[w] < bx)) {
-            bv = redv[w];
-            bx = redi[w];
+        int bk = redk[0], bw = redt[0];
+#pragma unroll
+        for (int x = 1; x < 4; ++x)
+          if (redv[x] > bv || (redv[x] == bv && redk[x] < bk)) {
+            bv = redv[x];
+            bk = redk[x];
+            bw = redt[x];
           }
-        if (bx >= pr) bx = j;  // no comparable candidate (NaN column): keep the diagonal
-        spiv[j] = bx;
-        spivval = Ps[bx + j * kLeafLd];
-        pv[k0 + j] = k0 + bx;
-        if (spivval == T(0)) atomicMin(info, ((unsigned long long)a << 20) | (unsigned long long)(k0 + j));
-      }
-      __syncthreads();
-      const int p = spiv[j];
-      const T pivot = spivval;
-      if (p != j)
-        for (int c = tid; c < nb; c += kLuThreads) {
-          T t0 = Ps[j + c * kLeafLd];
-          Ps[j + c * kLeafLd] = Ps[p + c * kLeafLd];
-          Ps[p + c * kLeafLd] = t0;
+        if (tid == bw) {
+          done = true;
+#pragma unroll
+          for (int cc = 0; cc < kCW; ++cc) urow[j & 1][cc] = r[cc];
+          sppos[j & 1] = mypos;
+          pv[c0 + j] = c0 + mypos;
+          if (r[j] == T(0)) atomicMin(info, ((unsigned long long)a << 20) | (unsigned long long)(c0 + j));
+          mypos = j;
         }
-      __syncthreads();
-      if (pivot != T(0)) {
-        const T rinv = T(1) / pivot;
-        for (int i = j + 1 + tid; i < pr; i += kLuThreads) {
-          T l = Ps[i + j * kLeafLd] * rinv;
-          Ps[i + j * kLeafLd] = l;
-          for (int c = j + 1; c < nb; ++c) Ps[i + c * kLeafLd] -= l * Ps[j + c * kLeafLd];
+        __syncthreads();
+        if (own && tid != bw && !done) {
+          if (mypos == j) mypos = sppos[j & 1];  // the row displaced by the interchange
+          const T pivot = urow[j & 1][j];
+          if (pivot != T(0)) {
+            const T l = r[j] * (T(1) / pivot);
+            r[j] = l;
+#pragma unroll
+            for (int cc = j + 1; cc < kCW; ++cc) r[cc] -= l * urow[j & 1][cc];
+          }
         }
       }
-      __syncthreads();
     }
-    // panel back to global
-    for (int e = tid; e < pr * nb; e += kLuThreads) {
-      int i = e % pr, j = e / pr;
-      A[(k0 + i) + (int64_t)(k0 + j) * m_max] = Ps[i + j * kLeafLd];
-    }
-    // interchanges on the columns left and right of the panel
-    for (int c = tid; c < m; c += kLuThreads) {
-      if (c >= k0 && c < k0 + nb) continue;
-      T* col = A + (int64_t)c * m_max;
-      for (int j = 0; j < nb; ++j) {
-        int p = spiv[j];
-        if (p != j) {
-          T t0 = col[k0 + j];
-          col[k0 + j] = col[k0 + p];
-          col[k0 + p] = t0;
-        }
-      }
+    // store the panel by original row and record the new row order
+    if (own) {
+#pragma unroll
+      for (int cc = 0; cc < kCW; ++cc)
+        if (cc < cw) F[orig + (int64_t)(c0 + cc) * ldl] = r[cc];
     }
     __syncthreads();
-    const int rest = m - k0 - nb;
-    if (rest > 0) {
-      // U12 = L11^{-1} A12, one column per thread
-      for (int c = tid; c < rest; c += kLuThreads) {
-        T* col = A + (int64_t)(k0 + nb + c) * m_max + k0;
-        T x[kNB];
+    if (own) pm[c0 + mypos] = orig;
+    __syncthreads();
+    // inverses of the two new unit-lower diagonal 16 x 16 blocks of L
+    if (tid < 32) {
+      const int kb = 2 * c + (tid >> 4), cc = tid & 15;
+      if (kb < nbk) {
+        const int g0 = 16 * kb;
+        T x[16];
 #pragma unroll
-        for (int i = 0; i < kNB; ++i) x[i] = (i < nb) ? col[i] : T(0);
+        for (int i = 0; i < 16; ++i) {
+          T s = (i == cc) ? T(1) : T(0);
+          const int prow = pm[g0 + i];
 #pragma unroll
-        for (int i = 1; i < kNB; ++i) {
-          if (i < nb) {
-            T acc = x[i];
-#pragma unroll
-            for (int jj = 0; jj < kNB; ++jj)
-              if (jj < i) acc -= Ps[i + jj * kLeafLd] * x[jj];
-            x[i] = acc;
-          }
+          for (int jj = 0; jj < i; ++jj) s -= ((g0 + i < m) ? F[prow + (int64_t)(g0 + jj) * ldl] : T(0)) * x[jj];
+          x[i] = (i >= cc) ? s : T(0);
         }
 #pragma unroll
-        for (int i = 0; i < kNB; ++i)
-          if (i < nb) {
-            col[i] = x[i];
-            Us[i * kLeafLd + c] = x[i];
-          }
+        for (int i = 0; i < 16; ++i) IL[kb * 256 + i * 16 + cc] = x[i];
       }
-      __syncthreads();
-      // A22 -= L21 * U12 with 4x4 register tiles over 64x64 sub-blocks
-      const int tx = tid >> 4, ty = tid & 15;
-      for (int rb = 0; rb < rest; rb += 64)
-        for (int cb = 0; cb < rest; cb += 64) {
-          T acc[4][4];
-#pragma unroll
-          for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-              int r = rb + ty + 16 * ii, c = cb + tx + 16 * jj;
-              acc[ii][jj] = (r < rest && c < rest) ? A[(k0 + nb + r) + (int64_t)(k0 + nb + c) * m_max] : T(0);
-            }
-          for (int kk = 0; kk < nb; ++kk) {
-            T lv[4], uv[4];
-#pragma unroll
-            for (int ii = 0; ii < 4; ++ii) {
-              int r = rb + ty + 16 * ii;
-              lv[ii] = (r < rest) ? Ps[(nb + r) + kk * kLeafLd] : T(0);
-            }
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-              int c = cb + tx + 16 * jj;
-              uv[jj] = (c < rest) ? Us[kk * kLeafLd + c] : T(0);
-            }
-#pragma unroll
-            for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-              for (int jj = 0; jj < 4; ++jj) acc[ii][jj] -= lv[ii] * uv[jj];
-          }
-#pragma unroll
-          for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-              int r = rb + ty + 16 * ii, c = cb + tx + 16 * jj;
-              if (r < rest && c < rest) A[(k0 + nb + r) + (int64_t)(k0 + nb + c) * m_max] = acc[ii][jj];
-            }
-        }
     }
     __syncthreads();
   }
-  // composed permutation and reciprocal diagonal
-  int32_t* pm = perm + (int64_t)a * m_max;
-  T* ud = udinv + (int64_t)a * m_max;
-  for (int i = tid; i < m_max; i += kLuThreads) {
-    ud[i] = (i < m) ? T(1) / A[i + (int64_t)i * m_max] : T(1);
+  // pivoted order: F[i, :] <- F[perm[i], :], 32 columns at a time
+  for (int g = 0; g < nch; ++g) {
+    T r[kCW];
+    const bool own = tid < m;
+    const int src = own ? pm[tid] : 0;
+#pragma unroll
+    for (int cc = 0; cc < kCW; ++cc) {
+      const int col = kCW * g + cc;
+      r[cc] = (own && col < m) ? F[src + (int64_t)col * ldl] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cc = 0; cc < kCW; ++cc) {
+      const int col = kCW * g + cc;
+      if (own && col < m) F[tid + (int64_t)col * ldl] = r[cc];
+    }
+    __syncthreads();
+  }
+  int32_t* pmo = perm + (int64_t)a * ldl;
+  T* ud = udinv + (int64_t)a * ldl;
+  for (int i = tid; i < ldl; i += kLuThreads) {
+    pmo[i] = i < m ? pm[i] : i;
     if (i >= m) pv[i] = i;
+    ud[i] = (i < m) ? T(1) / F[i + (int64_t)i * ldl] : T(1);
   }
-  if (tid == 0) {
-    for (int i = 0; i < m_max; ++i) pm[i] = i;
-    for (int j = 0; j < m; ++j) {
-      int p = pv[j];
-      int t0 = pm[j];
-      pm[j] = pm[p];
-      pm[p] = t0;
+  // inverses of the upper-triangular diagonal blocks (padded rows: identity)
+  {
+    const int kb = tid >> 4, cc = tid & 15;
+    if (kb < nbk) {
+      const int g0 = 16 * kb;
+      T x[16];
+#pragma unroll
+      for (int i = 15; i >= 0; --i) {
+        T s = (i == cc) ? T(1) : T(0);
+#pragma unroll
+        for (int jj = i + 1; jj < 16; ++jj)
+          s -= ((g0 + i < m && g0 + jj < m) ? F[g0 + i + (int64_t)(g0 + jj) * ldl] : T(0)) * x[jj];
+        const T d = (g0 + i < m) ? F[g0 + i + (int64_t)(g0 + i) * ldl] : T(1);
+        x[i] = (i <= cc) ? s / d : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) IL[(ldl / 16 + kb) * 256 + i * 16 + cc] = x[i];
     }
   }
 }
 
 template <typename T, typename S>
-hipError_t launch_leaf_lu(hipStream_t s, int nleaf, int m_max, const int64_t* d_leaf_off, const S* D,
-                          int64_t ldd, T* lu, int32_t* piv, int32_t* perm, T* udinv,
-                          unsigned long long* info) {
+hipError_t launch_leaf_lu(hipStream_t s, int nleaf, int ldl, const int64_t* d_leaf_off, const S* D, int64_t ldd,
+                          T* lu, int32_t* piv, int32_t* perm, T* udinv, T* invl, unsigned long long* info) {
   if (nleaf == 0) return hipSuccess;
-  size_t smem = sizeof(T) * (size_t)(HODLR_MAX_LEAF * kNB * 2);
-  auto k = leaf_lu_kernel<T, S>;
-  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(nleaf), dim3(kLuThreads), smem, s, m_max, d_leaf_off, D, ldd, lu, piv, perm, udinv,
-                     info);
+  if (ldl % 16 || ldl > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((leaf_lu_kernel<T, S>), dim3(nleaf), dim3(kLuThreads), 0, s, ldl, d_leaf_off, D, ldd, lu, piv,
+                     perm, udinv, invl, info);
   return hipGetLastError();
 }
 
 template hipError_t launch_leaf_lu<double, double>(hipStream_t, int, int, const int64_t*, const double*, int64_t,
-                                                   double*, int32_t*, int32_t*, double*, unsigned long long*);
+                                                   double*, int32_t*, int32_t*, double*, double*,
+                                                   unsigned long long*);
 template hipError_t launch_leaf_lu<float, double>(hipStream_t, int, int, const int64_t*, const double*, int64_t,
-                                                  float*, int32_t*, int32_t*, float*, unsigned long long*);
+                                                  float*, int32_t*, int32_t*, float*, float*, unsigned long long*);
 template hipError_t launch_leaf_lu<float, float>(hipStream_t, int, int, const int64_t*, const float*, int64_t,
-                                                 float*, int32_t*, int32_t*, float*, unsigned long long*);
+                                                 float*, int32_t*, int32_t*, float*, float*, unsigned long long*);
 
 }  // namespace hodlr

@@ -16,44 +16,25 @@
 // Workgroup = 256 threads = 4 waves; tile <= 256 rows (wave w owns rows
 // 64w..64w+63), one chunk of 64 columns of Z and one chunk of <= 64 columns
 // of B1; the four waves' partial products are summed in LDS in fixed order.
-#include "internal.h"
+#include "mfma.h"
 
 namespace hodlr {
-
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-  typedef d4 V;
-  static __device__ __forceinline__ V mma(double a, double b, V c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // row (within a 16-row tile) held by register t of a lane in quad lq
-  static __device__ __forceinline__ int crow(int lq, int t) { return 4 * t + lq; }
-};
-template <>
-struct Mfma<float> {
-  typedef f4 V;
-  static __device__ __forceinline__ V mma(float a, float b, V c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int crow(int lq, int t) { return 4 * lq + t; }
-};
 
 constexpr int kLpThreads = 256;
 
 template <typename TZ, typename SA, typename SB, int MB>
-__global__ __launch_bounds__(kLpThreads) void level_pass_kernel(const Tile* __restrict__ tiles, int zchunks,
-                                                                int bchunks, TZ* Z, int64_t ldz, int nz,
-                                                                const SA* __restrict__ A1, int64_t lda, int ka,
-                                                                const TZ* __restrict__ W, int64_t w_ld,
-                                                                int64_t w_pstride, int node_shift,
-                                                                const SB* __restrict__ B1, int64_t ldb, int kb_total,
-                                                                TZ* __restrict__ P) {
+__global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* __restrict__ tiles, int zchunks,
+                                                                   int bchunks, TZ* Z, int64_t ldz, int nz,
+                                                                   const SA* __restrict__ A1, int64_t lda, int ka,
+                                                                   const TZ* __restrict__ W, int64_t w_ld,
+                                                                   int64_t w_pstride, int node_shift,
+                                                                   const SB* __restrict__ B1, int64_t ldb,
+                                                                   int kb_total, TZ* __restrict__ P) {
   using M = Mfma<TZ>;
   using V = typename M::V;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  TZ* red = reinterpret_cast<TZ*>(smem_raw);  // [4 waves][MB*16][64]
+  TZ* Ws = reinterpret_cast<TZ*>(smem_raw);   // update phase: W chunk [k][64]
+  TZ* red = reinterpret_cast<TZ*>(smem_raw);  // product phase: [4 waves][MB*16][64]
 
   const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
   const int bchunk = (int)(lid % bchunks);
@@ -62,90 +43,89 @@ __global__ __launch_bounds__(kLpThreads) void level_pass_kernel(const Tile* __re
   const Tile tl = tiles[tile];
   const int64_t row0 = tl.row0;
   const int nrows = tl.nrows;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int w = tid >> 6;
-  const int li = lane & 15, lq = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lq = lane >> 4;
   const int c0 = zchunk * 64;
   const int ncb = min(4, (nz - c0 + 15) >> 4);
   const int wr0 = 64 * w;  // first tile row of this wave
+  const int nks = (ka + 3) >> 2;
 
-  V acc[4][4];
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  if (ka > 0) {
+    const int nd = tl.node >> node_shift;
+    const TZ* Wn = W + (int64_t)(nd >> 1) * w_pstride + (int64_t)(nd & 1) * ka;
+    for (int e = tid; e < 64 * 4 * nks; e += kLpThreads) {  // rows padded to a whole K-step with zeros
+      const int c = e % 64, k = e / 64;
+      Ws[e] = (k < ka && c0 + c < nz) ? Wn[k + (int64_t)(c0 + c) * w_ld] : TZ(0);
+    }
+    __syncthreads();
+  }
+
+  auto load_z = [&](int rb, V (&dst)[4]) {
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int row = wr0 + 16 * rb + M::crow(lq, t);
         const int col = c0 + 16 * cb + li;
-        acc[rb][cb][t] = (cb < ncb && row < nrows && col < nz) ? Z[row0 + row + (int64_t)col * ldz] : TZ(0);
+        dst[cb][t] = (cb < ncb && row < nrows && col < nz) ? Z[row0 + row + (int64_t)col * ldz] : TZ(0);
       }
+  };
 
-  if (ka > 0) {
-    const int nd = tl.node >> node_shift;
-    const TZ* Wn = W + (int64_t)(nd >> 1) * w_pstride + (int64_t)(nd & 1) * ka;
-    for (int k0 = 0; k0 < ka; k0 += 4) {
-      const int kk = k0 + lq;
-      TZ av[4], bv[4];
+  const int kc0 = bchunk * 64;
+  const int kb = kb_total > 0 ? min(64, kb_total - kc0) : 0;
+  V pacc[MB][4];
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
-        const int row = wr0 + 16 * rb + li;
-        av[rb] = (row < nrows && kk < ka) ? -(TZ)A1[row0 + row + (int64_t)kk * lda] : TZ(0);
-      }
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        const int col = c0 + 16 * cb + li;
-        bv[cb] = (cb < ncb && kk < ka && col < nz) ? Wn[kk + (int64_t)col * w_ld] : TZ(0);
-      }
+    for (int cb = 0; cb < 4; ++cb) pacc[mb][cb] = vzero<V>();
+
+  V acc[4], nxt[4];
+  load_z(0, nxt);
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
+  for (int rb = 0; rb < 4; ++rb) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = nxt[cb];
+    if (rb < 3) load_z(rb + 1, nxt);  // next row block in flight while this one computes
+    if (ka > 0) {
+      const int row = wr0 + 16 * rb + li;
+      for (int ks = 0; ks < nks; ++ks) {
+        const int kk = 4 * ks + lq;
+        const TZ a = (row < nrows && kk < ka) ? -(TZ)A1[row0 + row + (int64_t)kk * lda] : TZ(0);
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
-          if (cb < ncb) acc[rb][cb] = M::mma(av[rb], bv[cb], acc[rb][cb]);
-    }
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+          if (cb < ncb) acc[cb] = M::mma(a, Ws[kk * 64 + 16 * cb + li], acc[cb]);
+      }
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const int row = wr0 + 16 * rb + M::crow(lq, t);
+          const int rr = wr0 + 16 * rb + M::crow(lq, t);
           const int col = c0 + 16 * cb + li;
-          if (cb < ncb && row < nrows && col < nz) Z[row0 + row + (int64_t)col * ldz] = acc[rb][cb][t];
+          if (cb < ncb && rr < nrows && col < nz) Z[row0 + rr + (int64_t)col * ldz] = acc[cb][t];
         }
-  }
-
-  if (kb_total > 0) {
-    const int kc0 = bchunk * 64;
-    const int kb = min(64, kb_total - kc0);
-    V pacc[MB][4];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb) pacc[mb][cb] = V{0, 0, 0, 0};
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    }
+    if (kb > 0) {
+      // the accumulator register t holds exactly the B operand (4 rows x 16 columns) of one K-step
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int row = wr0 + 16 * rb + M::crow(lq, t);
+        const int rr = wr0 + 16 * rb + M::crow(lq, t);
         TZ bo[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
           const int kr = 16 * mb + li;
-          bo[mb] = (row < nrows && kr < kb) ? (TZ)B1[row0 + row + (int64_t)(kc0 + kr) * ldb] : TZ(0);
+          bo[mb] = (rr < nrows && kr < kb) ? (TZ)B1[row0 + rr + (int64_t)(kc0 + kr) * ldb] : TZ(0);
         }
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-          for (int cb = 0; cb < 4; ++cb) {
-            // B operand: lane holds Z[K-row lq of this step][column li]; the
-            // accumulator register t of the lane holds exactly that element.
-            if (cb < ncb) pacc[mb][cb] = M::mma(bo[mb], acc[rb][cb][t], pacc[mb][cb]);
-          }
+          for (int cb = 0; cb < 4; ++cb)
+            if (cb < ncb) pacc[mb][cb] = M::mma(bo[mb], acc[cb][t], pacc[mb][cb]);
       }
-    // fixed-order cross-wave sum
+    }
+  }
+
+  if (kb > 0) {
     constexpr int kRows = MB * 16;
+    if (ka > 0) __syncthreads();  // W chunk no longer read: its LDS becomes the reduction buffer
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -161,11 +141,11 @@ __global__ __launch_bounds__(kLpThreads) void level_pass_kernel(const Tile* __re
       const int kr = e % kb, cw = e / kb;
       const int col = c0 + cw;
       if (col < nz) {
-        TZ s = red[(0 * kRows + kr) * 64 + cw];
-        s += red[(1 * kRows + kr) * 64 + cw];
-        s += red[(2 * kRows + kr) * 64 + cw];
-        s += red[(3 * kRows + kr) * 64 + cw];
-        Pt[(kc0 + kr) + (int64_t)col * kb_total] = s;
+        TZ sum = red[(0 * kRows + kr) * 64 + cw];
+        sum += red[(1 * kRows + kr) * 64 + cw];
+        sum += red[(2 * kRows + kr) * 64 + cw];
+        sum += red[(3 * kRows + kr) * 64 + cw];
+        Pt[(kc0 + kr) + (int64_t)col * kb_total] = sum;
       }
     }
   }
@@ -182,7 +162,9 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, TZ* Z
   const int64_t grid = (int64_t)ntiles * zchunks * bchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
   const int mbn = kb > 0 ? (min(kb, 64) + 15) / 16 : 1;
-  const size_t smem = kb > 0 ? sizeof(TZ) * 4 * 16 * mbn * 64 : 0;
+  const size_t smem_red = kb > 0 ? sizeof(TZ) * 4 * 16 * mbn * 64 : 0;
+  const size_t smem_w = ka > 0 ? sizeof(TZ) * 64 * (size_t)((ka + 3) / 4 * 4) : 0;
+  const size_t smem = smem_red > smem_w ? smem_red : smem_w;
 #define HODLR_LP(MBV)                                                                                        \
   {                                                                                                          \
     auto k = level_pass_kernel<TZ, SA, SB, MBV>;                                                             \
