@@ -6,11 +6,11 @@
 // The products V^T Y arrive as per-tile partial sums (level pass) or as
 // segment sums of them; they are summed here in fixed order.
 //
-// couple_factor: one workgroup per parent; K is formed and LU-factored with
-//   partial pivoting in LDS (largest magnitude, lowest row on ties) and the
-//   right-hand sides [V_a^T Y_big(I_a, 1:R_l); V_b^T Y_big(I_b, 1:R_l)] of
-//   eq. "e:node1" are summed into W; the MFMA block solver then overwrites W
-//   with K^{-1} W.  The LU of K is stored zero-padded to kp x kp (kp = 2r
+// couple_factor: one workgroup per parent; K is formed in LDS and LU-factored
+//   with partial pivoting by one wave (largest magnitude, lowest row on ties)
+//   while the other waves sum the right-hand sides
+//   [V_a^T Y_big(I_a, 1:R_l); V_b^T Y_big(I_b, 1:R_l)] of eq. "e:node1" into
+//   W; the MFMA block solver then overwrites W with K^{-1} W.  The LU of K is stored zero-padded to kp x kp (kp = 2r
 //   rounded up to 16) so the block solver needs no bounds checks.
 // couple_solve: one wave per parent; w = K^{-1} [V_a^T x_a; V_b^T x_b]
 //   (eq. "e:node3") or the transposed solve used by the adjoint.
@@ -164,11 +164,8 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp
                                                                    int level, int L) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* K = reinterpret_cast<T*>(smem_raw);  // n2 x n2, col-major
-  __shared__ T redv[kCfThreads / 64];
-  __shared__ int redi[kCfThreads / 64];
   __shared__ int spiv[2 * HODLR_MAX_RANK];
   __shared__ int sperm[2 * HODLR_MAX_RANK];
-  __shared__ T spivval;
 
   const int g = blockIdx.x;
   const int a = 2 * g, b = 2 * g + 1;
@@ -191,64 +188,80 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp
     K[i + j * n2] = v;
   }
   __syncthreads();
-  for (int j = 0; j < n2; ++j) {
-    T best = T(-1);
-    int bi = 0x7fffffff;
-    if (tid >= j && tid < n2) {
-      best = fabs(K[tid + j * n2]);
-      bi = tid;
-    }
+  if (wid == 0) {
+    // LU with partial pivoting by one wave (rows over lanes, no block barriers)
+    for (int j = 0; j < n2; ++j) {
+      T best = T(-1);
+      int bi = 0x7fffffff;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      T ov = __shfl_xor(best, off, 64);
-      int oi = __shfl_xor(bi, off, 64);
-      if (ov > best || (ov == best && oi < bi)) {
-        best = ov;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      redv[wid] = best;
-      redi[wid] = bi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      T bv = redv[0];
-      int bx = redi[0];
-      for (int w = 1; w < kCfThreads / 64; ++w)
-        if (redv[w] > bv || (redv[w] == bv && redi[w] < bx)) {
-          bv = redv[w];
-          bx = redi[w];
+      for (int sl = 0; sl < 2; ++sl) {
+        const int row = sl * 64 + lane;
+        if (row >= j && row < n2) {
+          T v = fabs(K[row + j * n2]);
+          if (!(v == v)) v = T(INFINITY);
+          if (v > best || (v == best && row < bi)) {
+            best = v;
+            bi = row;
+          }
         }
-      if (bx >= n2) bx = j;  // no comparable candidate (NaN column): keep the diagonal
-      spiv[j] = bx;
-      spivval = K[bx + j * n2];
-      if (spivval == T(0))
-        atomicMin(info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16) |
-                            (unsigned long long)j);
-    }
-    __syncthreads();
-    const int p = spiv[j];
-    const T pivot = spivval;
-    if (p != j)
-      for (int c = tid; c < n2; c += kCfThreads) {
-        T t0 = K[j + c * n2];
-        K[j + c * n2] = K[p + c * n2];
-        K[p + c * n2] = t0;
       }
-    __syncthreads();
-    if (pivot != T(0)) {
-      const T rinv = T(1) / pivot;
-      const int rem = n2 - j - 1;
-      for (int i = j + 1 + tid; i < n2; i += kCfThreads) K[i + j * n2] *= rinv;
-      __syncthreads();
-      for (int e = tid; e < rem * rem; e += kCfThreads) {
-        const int i = j + 1 + e % rem, c = j + 1 + e / rem;
-        K[i + c * n2] -= K[i + j * n2] * K[j + c * n2];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const T ov = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bi = oi;
+        }
       }
+      const int p = (bi < n2) ? bi : j;
+      if (lane == 0) {
+        spiv[j] = p;
+        if (K[p + j * n2] == T(0))
+          atomicMin(info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16) |
+                              (unsigned long long)j);
+      }
+      if (p != j) {
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+          const int c = sl * 64 + lane;
+          if (c < n2) {
+            const T t0 = K[j + c * n2];
+            K[j + c * n2] = K[p + c * n2];
+            K[p + c * n2] = t0;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const T pivot = K[j + j * n2];
+      if (pivot != T(0)) {
+        const T rinv = T(1) / pivot;
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+          const int row = sl * 64 + lane;
+          if (row > j && row < n2) {
+            const T l = K[row + j * n2] * rinv;
+            K[row + j * n2] = l;
+            for (int c = j + 1; c < n2; ++c) K[row + c * n2] -= l * K[j + c * n2];
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __syncthreads();
+  } else {
+    // right-hand sides of eq. "e:node1", unpermuted (the block solver applies the pivots)
+    T* Wg = W + (int64_t)g * n2 * Rp;
+    for (int64_t e = tid - 64; e < (int64_t)n2 * Rp; e += kCfThreads - 64) {
+      const int i = (int)(e % n2), cc = (int)(e / n2);
+      const int node = i < r ? a : b;
+      Wg[e] = seg_sum(segs, seg_start, node, elems, (i % r) + (int64_t)cc * r);
+    }
   }
+  __syncthreads();
   // store the factors (zero-padded kp x kp), the composed permutation and the reciprocal diagonal
   T* Kg = Klu + (int64_t)g * kp * kp;
   for (int e = tid; e < kp * kp; e += kCfThreads) {
@@ -301,13 +314,6 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp
 #pragma unroll
       for (int i = 0; i < 16; ++i) dst[i * 16 + cc] = x[i];
     }
-  }
-  // right-hand sides of eq. "e:node1", unpermuted (the block solver applies the pivots)
-  T* Wg = W + (int64_t)g * n2 * Rp;
-  for (int64_t e = tid; e < (int64_t)n2 * Rp; e += kCfThreads) {
-    const int i = (int)(e % n2), cc = (int)(e / n2);
-    const int node = i < r ? a : b;
-    Wg[e] = seg_sum(segs, seg_start, node, elems, (i % r) + (int64_t)cc * r);
   }
 }
 

@@ -121,13 +121,18 @@ struct DevMem {
 };
 
 // Reduction plan of a product whose node level is p, computed on tiles of level q >= p.
+// Tile partials are summed in stages of at most kSegTiles items (fixed order) until every
+// node has at most kSegTiles partial sums left; the coupling kernels add those.
+struct ProdStage {
+  int nsegs = 0;
+  int2* d_desc = nullptr;  // per output segment: first input item, count
+};
 struct ProdPlan {
   int nnodes = 0;
-  bool reduced = false;
-  int nsegs = 0;
   int maxcount = 0;
+  std::vector<ProdStage> stages;  // empty: the coupling kernels read tile partials directly
+  size_t buf_items[2] = {0, 0};   // ping-pong regions of the segment buffer, in items
   int32_t* d_seg_start = nullptr;
-  int2* d_desc = nullptr;
 };
 
 }  // namespace
@@ -251,31 +256,38 @@ hodlr_status make_prod(hodlr_factors* F, int q, int p, hipStream_t st) {
   pp.nnodes = 1 << p;
   const int stride = 1 << (q - p);
   const std::vector<int>& ts = F->tile_start[q];
-  std::vector<int32_t> seg_start(pp.nnodes + 1, 0);
-  std::vector<int2> desc;
-  for (int i = 0; i < pp.nnodes; ++i) pp.maxcount = std::max(pp.maxcount, ts[(i + 1) * stride] - ts[i * stride]);
-  pp.reduced = pp.maxcount > kSegTiles;
-  for (int i = 0; i < pp.nnodes; ++i) {
-    const int t0 = ts[i * stride], t1 = ts[(i + 1) * stride];
-    if (!pp.reduced) {
-      seg_start[i] = t0;
-      continue;
+  // items of each node: initially its tiles
+  std::vector<int> start(pp.nnodes + 1);
+  for (int i = 0; i <= pp.nnodes; ++i) start[i] = ts[i * stride];
+  for (int i = 0; i < pp.nnodes; ++i) pp.maxcount = std::max(pp.maxcount, start[i + 1] - start[i]);
+  int stage = 0;
+  while (true) {
+    int mx = 0;
+    for (int i = 0; i < pp.nnodes; ++i) mx = std::max(mx, start[i + 1] - start[i]);
+    if (mx <= kSegTiles) break;
+    std::vector<int2> desc;
+    std::vector<int> nstart(pp.nnodes + 1);
+    for (int i = 0; i < pp.nnodes; ++i) {
+      nstart[i] = (int)desc.size();
+      for (int t = start[i]; t < start[i + 1]; t += kSegTiles)
+        desc.push_back(int2{t, std::min(kSegTiles, start[i + 1] - t)});
     }
-    seg_start[i] = (int)desc.size();
-    for (int t = t0; t < t1; t += kSegTiles) desc.push_back(int2{t, std::min(kSegTiles, t1 - t)});
-  }
-  seg_start[pp.nnodes] = pp.reduced ? (int)desc.size() : ts[pp.nnodes * stride];
-  pp.nsegs = pp.reduced ? (int)desc.size() : 0;
-  hodlr_status s = F->mem.alloc(&pp.d_seg_start, seg_start.size());
-  if (s) return s;
-  if (hipMemcpy(pp.d_seg_start, seg_start.data(), seg_start.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
-    return HODLR_ERR_HIP;
-  if (pp.reduced) {
-    s = F->mem.alloc(&pp.d_desc, desc.size());
+    nstart[pp.nnodes] = (int)desc.size();
+    ProdStage ps;
+    ps.nsegs = (int)desc.size();
+    hodlr_status s = F->mem.alloc(&ps.d_desc, desc.size());
     if (s) return s;
-    if (hipMemcpy(pp.d_desc, desc.data(), desc.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(ps.d_desc, desc.data(), desc.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
       return HODLR_ERR_HIP;
+    pp.buf_items[stage & 1] = std::max(pp.buf_items[stage & 1], desc.size());
+    pp.stages.push_back(ps);
+    start = nstart;
+    ++stage;
   }
+  hodlr_status s = F->mem.alloc(&pp.d_seg_start, start.size());
+  if (s) return s;
+  if (hipMemcpy(pp.d_seg_start, start.data(), start.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return HODLR_ERR_HIP;
   F->prods[key] = pp;
   (void)st;
   return HODLR_OK;
@@ -360,7 +372,7 @@ hodlr_status allocate_factors(hodlr_factors* F) {
     const size_t elems = (size_t)F->ranks[p - 1] * F->Rp[p];
     pmax = std::max(pmax, (size_t)F->ntiles[q] * elems);
     const ProdPlan& pp = F->prods[{q, p}];
-    if (pp.reduced) segmax = std::max(segmax, (size_t)pp.nsegs * elems);
+    segmax = std::max(segmax, (pp.buf_items[0] + pp.buf_items[1]) * elems);
   }
   if ((s = M.alloc(&b, (size_t)kk * ts))) return s;
   F->Klu = b;
@@ -390,12 +402,14 @@ template <typename T>
 hodlr_status prod_segments(hodlr_factors* F, hipStream_t st, int q, int p, int64_t elems, T* P, T* segbuf,
                            const T** segs, const int32_t** seg_start) {
   const ProdPlan& pp = F->prods.at({q, p});
-  if (pp.reduced) {
-    HL("segment_reduce", launch_segment_reduce<T>(st, pp.nsegs, pp.d_desc, elems, P, segbuf));
-    *segs = segbuf;
-  } else {
-    *segs = P;
+  const T* in = P;
+  T* region[2] = {segbuf, segbuf + pp.buf_items[0] * elems};
+  for (size_t k = 0; k < pp.stages.size(); ++k) {
+    T* out = region[k & 1];
+    HL("segment_reduce", launch_segment_reduce<T>(st, pp.stages[k].nsegs, pp.stages[k].d_desc, elems, in, out));
+    in = out;
   }
+  *segs = in;
   *seg_start = pp.d_seg_start;
   return HODLR_OK;
 }
@@ -501,7 +515,7 @@ hodlr_status ensure_ws(hodlr_factors* F, int nrhs) {
     for (int q : {fwd_prod_tiles(F, p), adj_prod_tiles(F, p)}) {
       pmax = std::max(pmax, (size_t)F->ntiles[q] * elems);
       const ProdPlan& pp = F->prods[{q, p}];
-      if (pp.reduced) segmax = std::max(segmax, (size_t)pp.nsegs * elems);
+      segmax = std::max(segmax, (pp.buf_items[0] + pp.buf_items[1]) * elems);
     }
   }
   for (int p = 0; p < L; ++p) wmax = std::max(wmax, (size_t)(int64_t(1) << p) * 2 * F->ranks[p] * nrhs);

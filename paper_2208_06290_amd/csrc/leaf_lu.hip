@@ -12,8 +12,8 @@
 //   3. the panel (rows below, 32 columns) is factored with one thread per row,
 //      the row held in registers: pivot = largest magnitude, lowest current
 //      position on ties (LAPACK idamax), rows are not moved - each thread
-//      tracks its position, the winner broadcasts its row through LDS, two
-//      barriers per column.
+//      tracks its position; each wave publishes its best candidate's row in
+//      LDS and every thread selects the winner, one barrier per column.
 // Entries are stored by original row while factoring (later interchanges move
 // no data); a final pass writes them in pivoted order.
 //
@@ -43,11 +43,10 @@ __global__ __launch_bounds__(kLuThreads) void leaf_lu_kernel(int ldl, const int6
   using V = typename M::V;
   __shared__ T stage[256 * kCW];  // panel rows, row-major [row][32]
   __shared__ T xk[2][16 * kCW];   // published X_k [row][col]
-  __shared__ T urow[2][kCW];      // pivot row of the current column
+  __shared__ T crow_[2][4][kCW];  // per wave: the row of its best pivot candidate
+  __shared__ T cval[2][4];        // per wave: |candidate|
+  __shared__ int ckey[2][4];      // per wave: candidate position (INT_MAX: none)
   __shared__ int pm[256];         // position -> original (leaf-local) row
-  __shared__ T redv[4];
-  __shared__ int redk[4], redt[4];
-  __shared__ int sppos[2], spt[2];
 
   const int a = blockIdx.x;
   const int64_t o = leaf_off[a];
@@ -154,55 +153,56 @@ __global__ __launch_bounds__(kLuThreads) void leaf_lu_kernel(int ldl, const int6
 #pragma unroll
     for (int j = 0; j < kCW; ++j) {
       if (j < cw) {
+        // one barrier per column: each wave publishes its best candidate (value,
+        // position, whole row); every thread then picks the winner of the four
+        const int sb = j & 1;
         const bool cand = own && !done;
         T v = cand ? fabs(r[j]) : T(-1);
         if (cand && !(v == v)) v = T(INFINITY);  // a NaN can still be chosen
         int key = cand ? mypos : 0x7fffffff;
-        int who = tid;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
           const T ov = __shfl_xor(v, off, 64);
           const int ok = __shfl_xor(key, off, 64);
-          const int ow = __shfl_xor(who, off, 64);
           if (ov > v || (ov == v && ok < key)) {
             v = ov;
             key = ok;
-            who = ow;
           }
+        }
+        if (cand && mypos == key) {
+#pragma unroll
+          for (int cc = 0; cc < kCW; ++cc) crow_[sb][w][cc] = r[cc];
         }
         if (lane == 0) {
-          redv[w] = v;
-          redk[w] = key;
-          redt[w] = who;
+          cval[sb][w] = v;
+          ckey[sb][w] = key;
         }
         __syncthreads();
-        T bv = redv[0];
-        int bk = redk[0], bw = redt[0];
+        T bv = cval[sb][0];
+        int bk = ckey[sb][0], bw = 0;
 #pragma unroll
         for (int x = 1; x < 4; ++x)
-          if (redv[x] > bv || (redv[x] == bv && redk[x] < bk)) {
-            bv = redv[x];
-            bk = redk[x];
-            bw = redt[x];
+          if (cval[sb][x] > bv || (cval[sb][x] == bv && ckey[sb][x] < bk)) {
+            bv = cval[sb][x];
+            bk = ckey[sb][x];
+            bw = x;
           }
-        if (tid == bw) {
-          done = true;
+        const T* prow = crow_[sb][bw];
+        if (cand) {
+          if (mypos == bk) {  // this row is the pivot of column j
+            done = true;
+            pv[c0 + j] = c0 + bk;
+            if (r[j] == T(0)) atomicMin(info, ((unsigned long long)a << 20) | (unsigned long long)(c0 + j));
+            mypos = j;
+          } else {
+            if (mypos == j) mypos = bk;  // the row displaced by the interchange
+            const T pivot = prow[j];
+            if (pivot != T(0)) {
+              const T l = r[j] * (T(1) / pivot);
+              r[j] = l;
 #pragma unroll
-          for (int cc = 0; cc < kCW; ++cc) urow[j & 1][cc] = r[cc];
-          sppos[j & 1] = mypos;
-          pv[c0 + j] = c0 + mypos;
-          if (r[j] == T(0)) atomicMin(info, ((unsigned long long)a << 20) | (unsigned long long)(c0 + j));
-          mypos = j;
-        }
-        __syncthreads();
-        if (own && tid != bw && !done) {
-          if (mypos == j) mypos = sppos[j & 1];  // the row displaced by the interchange
-          const T pivot = urow[j & 1][j];
-          if (pivot != T(0)) {
-            const T l = r[j] * (T(1) / pivot);
-            r[j] = l;
-#pragma unroll
-            for (int cc = j + 1; cc < kCW; ++cc) r[cc] -= l * urow[j & 1][cc];
+              for (int cc = j + 1; cc < kCW; ++cc) r[cc] -= l * prow[cc];
+            }
           }
         }
       }
