@@ -158,6 +158,7 @@ struct hodlr_factors {
   int32_t* d_rpre = nullptr;
   std::vector<Tile*> d_tiles;                 // per tile level q = 0..L
   std::vector<int> ntiles;                    // per q
+  std::vector<int> tiles_aligned;             // per q: every tile height is a multiple of 16
   std::vector<std::vector<int>> tile_start;   // per q, 2^q + 1
   std::map<std::pair<int, int>, ProdPlan> prods;
   // factors (T = compute element type)
@@ -301,11 +302,15 @@ hodlr_status plan(hodlr_factors* F) {
   const int L = F->L;
   F->d_tiles.assign(L + 1, nullptr);
   F->ntiles.assign(L + 1, 0);
+  F->tiles_aligned.assign(L + 1, 0);
   F->tile_start.assign(L + 1, {});
   std::vector<Tile> tl;
   for (int q = 0; q <= L; ++q) {
     build_tiles(F, q, tl, F->tile_start[q]);
     F->ntiles[q] = (int)tl.size();
+    F->tiles_aligned[q] = 1;
+    for (const Tile& t : tl)
+      if (t.nrows % 16) F->tiles_aligned[q] = 0;
     hodlr_status s = F->mem.alloc(&F->d_tiles[q], tl.size());
     if (s) return s;
     if (hipMemcpy(F->d_tiles[q], tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess)
@@ -430,7 +435,7 @@ hodlr_status run_factor(hodlr_factors* F, hipStream_t st) {
                                             tp<T>(F->invl), U, F->ldu, Y, N, F->R)));
   if (L > 0) {
     // products V^T Y for the children of level L-1 (the leaves)
-    HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], Y, N, F->R, (const T*)nullptr, N, 0,
+    HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], F->tiles_aligned[L], Y, N, F->R, (const T*)nullptr, N, 0,
                                                  (const T*)nullptr, 0, 0, 0, V + (int64_t)F->Rp[L - 1] * F->ldv,
                                                  F->ldv, F->ranks[L - 1], tp<T>(F->P))));
     for (int p = L - 1; p >= 0; --p) {
@@ -453,12 +458,12 @@ hodlr_status run_factor(hodlr_factors* F, hipStream_t st) {
                                                 tp<T>(F->Kinv) + F->kioff[p], tp<T>(F->W), 2 * r, Rp)));
       if (p > 0 && r > 0) {
         HL("level_pass",
-           (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], Y, N, Rp, Y + (int64_t)Rp * N, N, r,
+           (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], F->tiles_aligned[q], Y, N, Rp, Y + (int64_t)Rp * N, N, r,
                                        tp<T>(F->W), 2 * r, (int64_t)2 * r * Rp, 0,
                                        V + (int64_t)F->Rp[p - 1] * F->ldv, F->ldv, F->ranks[p - 1], tp<T>(F->P))));
       } else if (p > 0) {
         // rank-0 children: no update; products for level p still needed
-        HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], Y, N, Rp, (const T*)nullptr, N,
+        HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], F->tiles_aligned[q], Y, N, Rp, (const T*)nullptr, N,
                                                      0, (const T*)nullptr, 0, 0, 0,
                                                      V + (int64_t)F->Rp[p - 1] * F->ldv, F->ldv, F->ranks[p - 1],
                                                      tp<T>(F->P))));
@@ -554,7 +559,7 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
     HL("leaf_solve", (launch_leaf_trsm<T, T>(st, 0, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->perm,
                                              tp<T>(F->invl), X, ldx, X, ldx, nrhs)));
     if (L == 0) return HODLR_OK;
-    HL("solve_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], X, ldx, nrhs, (const T*)nullptr, N,
+    HL("solve_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], F->tiles_aligned[L], X, ldx, nrhs, (const T*)nullptr, N,
                                                  0, (const T*)nullptr, 0, 0, 0, V + (int64_t)F->Rp[L - 1] * F->ldv,
                                                  F->ldv, F->ranks[L - 1], P)));
     for (int p = L - 1; p >= 0; --p) {
@@ -572,7 +577,7 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
       }
       const int kb = p > 0 ? F->ranks[p - 1] : 0;
       if (r == 0 && kb == 0) continue;
-      HL("solve_pass", (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], X, ldx, nrhs,
+      HL("solve_pass", (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], F->tiles_aligned[q], X, ldx, nrhs,
                                                    Y + (int64_t)F->Rp[p] * N, N, r, w, 2 * r, (int64_t)2 * r * nrhs, 0,
                                                    p > 0 ? V + (int64_t)F->Rp[p - 1] * F->ldv : nullptr, F->ldv, kb,
                                                    P)));
@@ -581,7 +586,7 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
   }
   // adjoint: top level first, transposed coupling solves, leaves last
   if (L > 0) {
-    HL("adjoint_pass", (launch_level_pass<T, S, T>(st, F->ntiles[1], F->d_tiles[1], X, ldx, nrhs, (const S*)nullptr,
+    HL("adjoint_pass", (launch_level_pass<T, S, T>(st, F->ntiles[1], F->d_tiles[1], F->tiles_aligned[1], X, ldx, nrhs, (const S*)nullptr,
                                                    N, 0, (const T*)nullptr, 0, 0, 0, Y, N, F->ranks[0], P)));
     for (int p = 0; p < L; ++p) {
       const int q = p + 1;
@@ -599,7 +604,7 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
       const int tq = q < L ? q + 1 : L;
       const int kb = q < L ? F->ranks[q] : 0;
       if (r == 0 && kb == 0) continue;
-      HL("adjoint_pass", (launch_level_pass<T, S, T>(st, F->ntiles[tq], F->d_tiles[tq], X, ldx, nrhs,
+      HL("adjoint_pass", (launch_level_pass<T, S, T>(st, F->ntiles[tq], F->d_tiles[tq], F->tiles_aligned[tq], X, ldx, nrhs,
                                                      V + (int64_t)F->Rp[p] * F->ldv, F->ldv, r, w, 2 * r,
                                                      (int64_t)2 * r * nrhs, tq - q,
                                                      q < L ? Y + (int64_t)F->Rp[q] * N : nullptr, N, kb, P)));
@@ -620,7 +625,7 @@ hodlr_status matvec_impl(hodlr_factors* F, hipStream_t st, int trans, int nrhs, 
   const int64_t lda = trans ? F->ldv : F->ldu, ldb = trans ? F->ldu : F->ldv;
   if (L > 0 && F->R > 0) {
     double* leaves = tree + tree_slot(L, 0) * F->R * nrhs;
-    HL("mv_project", (launch_level_pass<double, double, S>(st, F->ntiles[L], F->d_tiles[L], const_cast<double*>(X),
+    HL("mv_project", (launch_level_pass<double, double, S>(st, F->ntiles[L], F->d_tiles[L], F->tiles_aligned[L], const_cast<double*>(X),
                                                            ldx, nrhs, (const double*)nullptr, 0, 0,
                                                            (const double*)nullptr, 0, 0, 0, Vb, ldb, F->R, leaves)));
     for (int l = L - 1; l >= 1; --l)
@@ -871,11 +876,11 @@ hodlr_status hodlr_grad(const hodlr_factors* Fc, int64_t nrhs, const double* X, 
     double* leaves = tree + tree_slot(L, 0) * F->R * n;
     if (F->storage == HODLR_F64)
       HL("grad_project", (launch_level_pass<double, double, double>(
-                             st, F->ntiles[L], F->d_tiles[L], const_cast<double*>(Xin), ldxin, n, (const double*)nullptr,
+                             st, F->ntiles[L], F->d_tiles[L], F->tiles_aligned[L], const_cast<double*>(Xin), ldxin, n, (const double*)nullptr,
                              0, 0, (const double*)nullptr, 0, 0, 0, static_cast<const double*>(Mv), ldm, F->R, leaves)));
     else
       HL("grad_project", (launch_level_pass<double, double, float>(
-                             st, F->ntiles[L], F->d_tiles[L], const_cast<double*>(Xin), ldxin, n, (const double*)nullptr,
+                             st, F->ntiles[L], F->d_tiles[L], F->tiles_aligned[L], const_cast<double*>(Xin), ldxin, n, (const double*)nullptr,
                              0, 0, (const double*)nullptr, 0, 0, 0, static_cast<const float*>(Mv), ldm, F->R, leaves)));
     for (int l = L - 1; l >= 1; --l)
       HL("grad_tree", launch_tree_sum(st, 1 << l, (int64_t)F->R * n, tree + tree_slot(l + 1, 0) * F->R * n,

@@ -84,8 +84,9 @@ hipError_t launch_block_trsm(hipStream_t s, int trans, int nblk, int ldl, int m,
 //   product: P_tile(0:kb, 0:nz) = B1(tile, 0:kb)^T * Z(tile, 0:nz)      (if kb > 0)
 // nd = tile.node >> node_shift; W for node nd starts at W + (nd >> 1) * w_pstride + (nd & 1) * ka, ld = w_ld.
 // P_tile starts at P + tile * kb * nz, col-major ld = kb.
+// tiles_aligned: every tile height is a multiple of 16 (enables the fast kernel).
 template <typename TZ, typename SA, typename SB>
-hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, TZ* Z, int64_t ldz, int nz,
+hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int tiles_aligned, TZ* Z, int64_t ldz, int nz,
                              const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld,
                              int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P);
 

@@ -34,7 +34,7 @@ constexpr int kLuThreads = 256;
 constexpr int kCW = 32;  // chunk (panel) width
 
 template <typename T, typename S>
-__global__ __launch_bounds__(kLuThreads) void leaf_lu_kernel(int ldl, const int64_t* __restrict__ leaf_off,
+__global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const int64_t* __restrict__ leaf_off,
                                                              const S* __restrict__ D, int64_t ldd, T* lu,
                                                              int32_t* __restrict__ piv, int32_t* __restrict__ perm,
                                                              T* __restrict__ udinv, T* invl,
@@ -51,22 +51,30 @@ __global__ __launch_bounds__(kLuThreads) void leaf_lu_kernel(int ldl, const int6
   const int a = blockIdx.x;
   const int64_t o = leaf_off[a];
   const int m = (int)(leaf_off[a + 1] - o);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lq = lane >> 4;
+  const int tid0 = threadIdx.x, w0 = __builtin_amdgcn_readfirstlane(tid0 >> 6);
   T* F = lu + (int64_t)a * ldl * ldl;  // by original row while factoring
   T* IL = invl + (int64_t)a * 2 * (ldl / 16) * 256;
   int32_t* pv = piv + (int64_t)a * ldl;
   const int nbk = (m + 15) >> 4;
   const int nch = (m + kCW - 1) / kCW;
 
-  for (int i = tid; i < 256; i += kLuThreads) pm[i] = i;
+  for (int i = tid0; i < 256; i += kLuThreads) pm[i] = i;
   // zero padding outside m x m (never touched by the factorization)
-  for (int64_t e = tid; e < (int64_t)ldl * ldl; e += kLuThreads) {
-    const int i = (int)(e % ldl), j = (int)(e / ldl);
-    if (i >= m || j >= m) F[e] = T(0);
+  if (m < ldl) {
+    for (int j = 0; j < ldl; ++j)
+      for (int i = tid0; i < ldl; i += kLuThreads)
+        if (i >= m || j >= m) F[i + (int64_t)j * ldl] = T(0);
   }
   __syncthreads();
 
   for (int c = 0; c < nch; ++c) {
+    // lane coordinates are re-derived from opaque copies in every chunk so the
+    // compiler cannot hoist lane-dependent addresses and constants out of the
+    // chunk loop (they would otherwise stay live and spill)
+    int tid = tid0, w = w0;
+    asm volatile("" : "+v"(tid));
+    asm volatile("" : "+s"(w));
+    const int lane = tid & 63, li = lane & 15, lq = lane >> 4;
     const int c0 = kCW * c;
     const int cw = min(kCW, m - c0);
     // 1. load the chunk in the current row order
@@ -207,78 +215,90 @@ __global__ __launch_bounds__(kLuThreads) void leaf_lu_kernel(int ldl, const int6
         }
       }
     }
-    // store the panel by original row and record the new row order
+    // store the panel by original row and record the new row order; the rows
+    // that became pivot rows also go to LDS as the chunk's 32 x 32 diagonal
+    // block (pivoted order), from which the diagonal-block inverses are formed
+    T* dblk = stage;  // [32][32] row-major; the panel no longer reads stage
     if (own) {
 #pragma unroll
       for (int cc = 0; cc < kCW; ++cc)
         if (cc < cw) F[orig + (int64_t)(c0 + cc) * ldl] = r[cc];
+      if (mypos < kCW) {
+#pragma unroll
+        for (int cc = 0; cc < kCW; ++cc) dblk[mypos * kCW + cc] = r[cc];
+      }
     }
     __syncthreads();
     if (own) pm[c0 + mypos] = orig;
-    __syncthreads();
-    // inverses of the two new unit-lower diagonal 16 x 16 blocks of L
-    if (tid < 32) {
-      const int kb = 2 * c + (tid >> 4), cc = tid & 15;
+    // inverses of the new 16 x 16 diagonal blocks: threads 0..31 invert the
+    // unit-lower L blocks, 32..63 the upper U blocks (one column each); rows
+    // beyond m act as identity
+    if (tid < 64) {
+      const int half = (tid >> 4) & 1;
+      int cc = tid & 15;
+      asm volatile("" : "+v"(cc));  // keeps the identity columns from being hoisted out of the chunk loop
+      const int kb = 2 * c + half;
+      const int g0 = 16 * kb;
+      const T* Bk = dblk + (16 * half) * kCW + 16 * half;  // element (i, j) at Bk[i * kCW + j]
       if (kb < nbk) {
-        const int g0 = 16 * kb;
         T x[16];
+        if (tid < 32) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          T s = (i == cc) ? T(1) : T(0);
-          const int prow = pm[g0 + i];
+          for (int i = 0; i < 16; ++i) {
+            T sacc = (i == cc) ? T(1) : T(0);
 #pragma unroll
-          for (int jj = 0; jj < i; ++jj) s -= ((g0 + i < m) ? F[prow + (int64_t)(g0 + jj) * ldl] : T(0)) * x[jj];
-          x[i] = (i >= cc) ? s : T(0);
+            for (int jj = 0; jj < i; ++jj) sacc -= ((g0 + i < m) ? Bk[i * kCW + jj] : T(0)) * x[jj];
+            x[i] = (i >= cc) ? sacc : T(0);
+          }
+#pragma unroll
+          for (int i = 0; i < 16; ++i) IL[kb * 256 + i * 16 + cc] = x[i];
+        } else {
+#pragma unroll
+          for (int i = 15; i >= 0; --i) {
+            T sacc = (i == cc) ? T(1) : T(0);
+#pragma unroll
+            for (int jj = i + 1; jj < 16; ++jj)
+              sacc -= ((g0 + i < m && g0 + jj < m) ? Bk[i * kCW + jj] : T(0)) * x[jj];
+            const T d = (g0 + i < m) ? Bk[i * kCW + i] : T(1);
+            x[i] = (i <= cc) ? sacc / d : T(0);
+          }
+#pragma unroll
+          for (int i = 0; i < 16; ++i) IL[(ldl / 16 + kb) * 256 + i * 16 + cc] = x[i];
         }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) IL[kb * 256 + i * 16 + cc] = x[i];
       }
+    } else if (tid < 64 + kCW && c0 + tid - 64 < ldl) {
+      const int j = tid - 64;
+      udinv[(int64_t)a * ldl + c0 + j] = (j < cw) ? T(1) / dblk[j * kCW + j] : T(1);
     }
     __syncthreads();
   }
-  // pivoted order: F[i, :] <- F[perm[i], :], 32 columns at a time
-  for (int g = 0; g < nch; ++g) {
-    T r[kCW];
-    const bool own = tid < m;
-    const int src = own ? pm[tid] : 0;
+  const int tid = tid0;
+  // pivoted order: F[i, :] <- F[perm[i], :], 32 columns at a time; nothing
+  // to do when no row moved
+  const bool moved = tid < m && pm[tid] != tid;
+  if (__syncthreads_or(moved)) {
+    const int src = tid < m ? pm[tid] : tid;
+    for (int g = 0; g < nch; ++g) {
+      T r[kCW];
 #pragma unroll
-    for (int cc = 0; cc < kCW; ++cc) {
-      const int col = kCW * g + cc;
-      r[cc] = (own && col < m) ? F[src + (int64_t)col * ldl] : T(0);
-    }
-    __syncthreads();
+      for (int cc = 0; cc < kCW; ++cc) {
+        const int col = min(kCW * g + cc, m - 1);
+        r[cc] = F[min(src, ldl - 1) + (int64_t)col * ldl];
+      }
+      __syncthreads();
+      if (moved) {
 #pragma unroll
-    for (int cc = 0; cc < kCW; ++cc) {
-      const int col = kCW * g + cc;
-      if (own && col < m) F[tid + (int64_t)col * ldl] = r[cc];
+        for (int cc = 0; cc < kCW; ++cc)
+          if (kCW * g + cc < m) F[tid + (int64_t)(kCW * g + cc) * ldl] = r[cc];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   int32_t* pmo = perm + (int64_t)a * ldl;
-  T* ud = udinv + (int64_t)a * ldl;
   for (int i = tid; i < ldl; i += kLuThreads) {
     pmo[i] = i < m ? pm[i] : i;
     if (i >= m) pv[i] = i;
-    ud[i] = (i < m) ? T(1) / F[i + (int64_t)i * ldl] : T(1);
-  }
-  // inverses of the upper-triangular diagonal blocks (padded rows: identity)
-  {
-    const int kb = tid >> 4, cc = tid & 15;
-    if (kb < nbk) {
-      const int g0 = 16 * kb;
-      T x[16];
-#pragma unroll
-      for (int i = 15; i >= 0; --i) {
-        T s = (i == cc) ? T(1) : T(0);
-#pragma unroll
-        for (int jj = i + 1; jj < 16; ++jj)
-          s -= ((g0 + i < m && g0 + jj < m) ? F[g0 + i + (int64_t)(g0 + jj) * ldl] : T(0)) * x[jj];
-        const T d = (g0 + i < m) ? F[g0 + i + (int64_t)(g0 + i) * ldl] : T(1);
-        x[i] = (i <= cc) ? s / d : T(0);
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) IL[(ldl / 16 + kb) * 256 + i * 16 + cc] = x[i];
-    }
+    if (i >= nch * kCW) udinv[(int64_t)a * ldl + i] = T(1);  // beyond the last chunk of a short leaf
   }
 }
 

@@ -13,18 +13,19 @@
 // owns the 16-row blocks b with b % 4 == w.  The inverses of the 16 x 16
 // diagonal blocks of L and U come with the factorization and are staged in
 // LDS per sweep, so every block step is a contraction: the owning wave forms
-// X_k = inv(M_kk) B_k
-// (the accumulator registers of B_k are exactly the B operands of that
-// product), publishes X_k through LDS (double buffered, one barrier per
-// step), and every wave applies B_b -= M_bk X_k to its blocks on MFMA with
-// operands fetched before the barrier.
+// X_k = inv(M_kk) B_k, publishes X_k through LDS (double buffered, one
+// barrier per step), and every wave applies B_b -= M_bk X_k to its blocks on
+// MFMA with operands fetched before the barrier.  The products run
+// transposed (X^T = B^T M^{-T}) so that accumulator rows are matrix rows on
+// the lanes: every global load and store covers whole 128-byte lines.
 #include "mfma.h"
 
 namespace hodlr {
 
 constexpr int kTsThreads = 256;
+constexpr int kTwLd = 17;  // padded row length of the owner's 16 x 16 turn-around buffer
 
-template <typename T, typename S, int TRANS>
+template <typename T, typename S, int TRANS, int NCB>
 __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int64_t* __restrict__ leaf_off,
                                                              int64_t ostride, int mfix, const T* __restrict__ lu,
                                                              const int32_t* __restrict__ perm,
@@ -34,10 +35,11 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
   using V = typename M::V;
   __shared__ T invA[16 * 256];     // inverse diagonal blocks of the current sweep, [kb][i][j]
   __shared__ T xk[2][16 * 64];     // published block X_k: [row][col]
+  __shared__ T tw[4][16 * kTwLd];  // per-wave turn-around of the owner's block
 
-  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
-  const int a = (int)(lid / nchunks);
-  const int chunk = (int)(lid % nchunks);
+  const int lid = (int)xcd_remap(blockIdx.x, gridDim.x);
+  const int a = lid / nchunks;
+  const int chunk = lid % nchunks;
   int64_t o;
   int m;
   if (leaf_off) {
@@ -47,28 +49,16 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
     o = (int64_t)a * ostride;
     m = mfix;
   }
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lq = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lq = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c0 = chunk * 64;
-  const int ncb = min(4, (ncols - c0 + 15) >> 4);
   const int nbk = (m + 15) >> 4;
   const T* F = lu + (int64_t)a * ldl * ldl;
   const int32_t* pm = perm + (int64_t)a * ldl;
   const int nbd = ldl >> 4;
   const T* DI = dinv + (int64_t)a * 2 * nbd * 256;  // [0][kb]: inv(L_kk), [1][kb]: inv(U_kk)
+  T* twv = tw[w];
 
-  // F(i, j) of the zero-padded factor block; U's padded diagonal reads as 1
-  auto Fe = [&](int i, int j) -> T { return F[i + (int64_t)j * ldl]; };
-  auto Ud = [&](int i) -> T { return i < m ? F[i + (int64_t)i * ldl] : T(1); };
-  // sweep matrix element (global indices): sweep 0 is lower, sweep 1 upper
-  auto Mel = [&](int sweep, int i, int j) -> T {
-    if (!TRANS) {
-      if (sweep == 0) return i == j ? T(1) : (i > j ? Fe(i, j) : T(0));   // L
-      return i == j ? Ud(i) : (i < j ? Fe(i, j) : T(0));                  // U
-    } else {
-      if (sweep == 0) return i == j ? Ud(i) : (i > j ? Fe(j, i) : T(0));  // U^T
-      return i == j ? T(1) : (i < j ? Fe(j, i) : T(0));                   // L^T
-    }
-  };
   // stage inv(M_kk) of a sweep: sweep 0 is L (trans 0) or U^T (trans 1), sweep 1 is U or L^T
   auto stage_inv = [&](int sweep) {
     const int which = TRANS ? 1 - sweep : sweep;
@@ -81,25 +71,27 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
 
   stage_inv(0);
 
-  // load the chunk (rows of P^T B for trans = 0) into accumulators
-  V acc[4][4];
+  // The chunk is held transposed: accumulator block (q, cb), register t holds
+  // X(16 (4 q + w) + li, c0 + 16 cb + crow(lq, t)), so the 16 lanes of a row
+  // group touch 16 consecutive rows of one column (whole 128-byte lines).
+  V acc[4][NCB];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * (4 * q + w) + li;
+    const int rowc = min(row, m - 1);
+    const int src = TRANS ? rowc : pm[rowc];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int row = 16 * (4 * q + w) + M::crow(lq, t);
-        const int col = c0 + 16 * cb + li;
-        T v = T(0);
-        if (cb < ncb && row < m && col < ncols) {
-          const int src = TRANS ? row : pm[row];
-          v = (T)B[o + src + (int64_t)col * ldb];
-        }
-        acc[q][cb][t] = v;
+        const int col = c0 + 16 * cb + M::crow(lq, t);
+        const T v = (T)B[o + src + (int64_t)min(col, ncols - 1) * ldb];
+        acc[q][cb][t] = (row < m && col < ncols) ? v : T(0);
       }
+  }
   __syncthreads();  // invA staged; B may alias X: all loads of the chunk precede any store
 
+  int step = 0;
 #pragma unroll
   for (int sweep = 0; sweep < 2; ++sweep) {
     if (sweep == 1) {
@@ -107,47 +99,59 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
       stage_inv(1);
       __syncthreads();
     }
-    for (int step = 0; step < nbk; ++step) {
-      const int k = sweep == 0 ? step : nbk - 1 - step;
-      T* xb = xk[step & 1];
-      if ((k & 3) == w) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (4 * q + w == k) {
+    for (int qq = 0; qq < 4; ++qq) {
+      const int q = sweep == 0 ? qq : 3 - qq;
+      for (int ww = 0; ww < 4; ++ww) {
+        const int wk = sweep == 0 ? ww : 3 - ww;
+        const int k = 4 * q + wk;
+        if (k >= nbk) continue;  // uniform
+        T* xb = xk[step & 1];
+        ++step;
+        if (w == wk) {
+          // X_k^T = B_k^T inv(M_kk)^T: the block turns around through LDS to
+          // become the A operand; the result stays in the accumulators and is
+          // published as X_k[row][col]
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
-              if (cb < ncb) {
-                V nv = vzero<V>();
+          for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                  nv = M::mma(invA[k * 256 + li * 16 + M::crow(lq, t)], acc[q][cb][t], nv);
-                acc[q][cb] = nv;
+            for (int t = 0; t < 4; ++t) twv[li * kTwLd + M::crow(lq, t)] = acc[q][cb][t];
+            V nv = vzero<V>();
 #pragma unroll
-                for (int t = 0; t < 4; ++t) xb[M::crow(lq, t) * 64 + 16 * cb + li] = nv[t];
-              }
+            for (int ks = 0; ks < 4; ++ks)
+              nv = M::mma(twv[(4 * ks + lq) * kTwLd + li], invA[k * 256 + li * 16 + 4 * ks + lq], nv);
+            acc[q][cb] = nv;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) xb[li * 64 + 16 * cb + M::crow(lq, t)] = nv[t];
           }
-      }
-      // B_b -= M_bk X_k for this wave's blocks on the far side of k; the factor
-      // operands do not depend on X_k and are fetched before the barrier
-      T av[4][4];
+        }
+        // B_b^T -= X_k^T M_bk^T for this wave's blocks on the far side of k; the
+        // factor operands M(16 b + li, 16 k + 4 ks + lq) do not depend on X_k
+        // and are fetched before the barrier (clamped in range, no branches)
+        T av[4][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int b = 4 * q + w;
-        const bool act = sweep == 0 ? (b > k && b < nbk) : (b < k);
+        for (int q2 = 0; q2 < 4; ++q2) {
+          if (sweep == 0 ? q2 < q : q2 > q) continue;  // never on the far side: resolved at compile time
+          const int b = min(4 * q2 + w, nbk - 1);
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) av[q][ks] = act ? -Mel(sweep, 16 * b + li, 16 * k + 4 * ks + lq) : T(0);
-      }
-      __syncthreads();
+          for (int ks = 0; ks < 4; ++ks) {
+            const int i = 16 * b + li, j = 16 * k + 4 * ks + lq;
+            av[q2][ks] = -(TRANS ? F[j + (int64_t)i * ldl] : F[i + (int64_t)j * ldl]);
+          }
+        }
+        __syncthreads();
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int b = 4 * q + w;
-        const bool act = sweep == 0 ? (b > k && b < nbk) : (b < k);
-        if (act) {
+        for (int q2 = 0; q2 < 4; ++q2) {
+          if (sweep == 0 ? q2 < q : q2 > q) continue;
+          const int b = 4 * q2 + w;
+          const bool act = (sweep == 0 ? (q2 > q || w > wk) : (q2 < q || w < wk)) && b < nbk;  // uniform
+          if (act) {
 #pragma unroll
-          for (int ks = 0; ks < 4; ++ks)
+            for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
-              if (cb < ncb) acc[q][cb] = M::mma(av[q][ks], xb[(4 * ks + lq) * 64 + 16 * cb + li], acc[q][cb]);
+              for (int cb = 0; cb < NCB; ++cb)
+                acc[q2][cb] = M::mma(xb[(4 * ks + lq) * 64 + 16 * cb + li], av[q2][ks], acc[q2][cb]);
+          }
         }
       }
     }
@@ -155,18 +159,19 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
 
   // store (the adjoint scatters rows through the permutation)
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * (4 * q + w) + li;
+    if (row < m) {
+      const int dst = TRANS ? pm[row] : row;
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+      for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int row = 16 * (4 * q + w) + M::crow(lq, t);
-        const int col = c0 + 16 * cb + li;
-        if (cb < ncb && row < m && col < ncols) {
-          const int dst = TRANS ? pm[row] : row;
-          X[o + dst + (int64_t)col * ldx] = acc[q][cb][t];
+        for (int t = 0; t < 4; ++t) {
+          const int col = c0 + 16 * cb + M::crow(lq, t);
+          if (col < ncols) X[o + dst + (int64_t)col * ldx] = acc[q][cb][t];
         }
-      }
+    }
+  }
 }
 
 template <typename T, typename S>
@@ -178,12 +183,16 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
   const int nchunks = (ncols + 63) / 64;
   const int64_t grid = (int64_t)nblk * nchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  if (trans)
-    hipLaunchKernelGGL((trsm_kernel<T, S, 1>), dim3((unsigned)grid), dim3(kTsThreads), 0, s, ldl, d_off, ostride,
-                       mfix, lu, perm, dinv, B, ldb, X, ldx, ncols, nchunks);
-  else
-    hipLaunchKernelGGL((trsm_kernel<T, S, 0>), dim3((unsigned)grid), dim3(kTsThreads), 0, s, ldl, d_off, ostride,
-                       mfix, lu, perm, dinv, B, ldb, X, ldx, ncols, nchunks);
+#define HODLR_TS(TR, NC)                                                                                  \
+  hipLaunchKernelGGL((trsm_kernel<T, S, TR, NC>), dim3((unsigned)grid), dim3(kTsThreads), 0, s, ldl, d_off, ostride, \
+                     mfix, lu, perm, dinv, B, ldb, X, ldx, ncols, nchunks)
+  // one 16-column block per chunk for narrow right-hand sides, four otherwise
+  if (trans) {
+    if (ncols <= 16) HODLR_TS(1, 1); else HODLR_TS(1, 4);
+  } else {
+    if (ncols <= 16) HODLR_TS(0, 1); else HODLR_TS(0, 4);
+  }
+#undef HODLR_TS
   return hipGetLastError();
 }
 

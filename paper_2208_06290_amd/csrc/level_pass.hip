@@ -1,5 +1,5 @@
-// Fused per-level pass over row tiles (Alg. "a:gpuf" lines with batched_gemm,
-// Alg. "a:gpus" lines with batched_gemm, restated on row tiles):
+// Fused per-level pass over row tiles (Alg. "a:gpuf" batched GEMMs and
+// Alg. "a:gpus" batched GEMMs, restated on row tiles):
 //
 //   update : Z(tile, 0:nz) -= A1(tile, 0:ka) * W_node(0:ka, 0:nz)
 //            factor: Y_big(I_a, 1:R_l) -= Y_a W_a        (eq. "e:node2")
@@ -8,20 +8,24 @@
 //            the partial sums of V^T Y (eq. "e:node1" right side and the T
 //            blocks of eq. "e:k") or of V^T x (eq. "e:node3") for the next level
 //
-// Both run on MFMA (f64 16x16x4 or f32 16x16x4).  The updated Z tile stays in
-// the accumulator registers and feeds the product directly as B operand: in
-// the accumulator layout each 4-register group holds 4 rows x 16 columns,
-// exactly one K-step of the product.
-//
 // Workgroup = 256 threads = 4 waves; tile <= 256 rows (wave w owns rows
 // 64w..64w+63), one chunk of 64 columns of Z and one chunk of <= 64 columns
-// of B1; the four waves' partial products are summed in LDS in fixed order.
+// of B1; the four waves' partial products are summed in LDS in a fixed order.
+//
+// Two kernels: level_pass_fast_kernel when tile heights, nz, ka and kb are
+// all multiples of 16 (the common case), level_pass_kernel otherwise.
 #include "mfma.h"
+
+#include <algorithm>
 
 namespace hodlr {
 
 constexpr int kLpThreads = 256;
 
+// General kernel: any tile height and any sizes, with clamped loads and
+// masked values and stores.  The updated Z tile stays in the accumulator
+// registers and feeds the product directly as B operand: in the accumulator
+// layout each 4-register group holds 4 rows x 16 columns, one K-step.
 template <typename TZ, typename SA, typename SB, int MB>
 __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* __restrict__ tiles, int zchunks,
                                                                    int bchunks, TZ* Z, int64_t ldz, int nz,
@@ -36,10 +40,10 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
   TZ* Ws = reinterpret_cast<TZ*>(smem_raw);   // update phase: W chunk [k][64]
   TZ* red = reinterpret_cast<TZ*>(smem_raw);  // product phase: [4 waves][MB*16][64]
 
-  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
-  const int bchunk = (int)(lid % bchunks);
-  const int zchunk = (int)((lid / bchunks) % zchunks);
-  const int64_t tile = lid / ((int64_t)bchunks * zchunks);
+  const int lid = (int)xcd_remap(blockIdx.x, gridDim.x);  // grid < 2^31: 32-bit index math
+  const int bchunk = lid % bchunks;
+  const int zchunk = (lid / bchunks) % zchunks;
+  const int tile = lid / (bchunks * zchunks);
   const Tile tl = tiles[tile];
   const int64_t row0 = tl.row0;
   const int nrows = tl.nrows;
@@ -59,6 +63,7 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
     __syncthreads();
   }
 
+  // loads are clamped into range and masked with a select: no branches, nothing drains the queue
   auto load_z = [&](int rb, V (&dst)[4]) {
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
@@ -66,7 +71,9 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
       for (int t = 0; t < 4; ++t) {
         const int row = wr0 + 16 * rb + M::crow(lq, t);
         const int col = c0 + 16 * cb + li;
-        dst[cb][t] = (cb < ncb && row < nrows && col < nz) ? Z[row0 + row + (int64_t)col * ldz] : TZ(0);
+        const bool ok = row < nrows && col < nz;
+        const TZ v = Z[row0 + min(row, nrows - 1) + (int64_t)min(col, nz - 1) * ldz];
+        dst[cb][t] = ok ? v : TZ(0);
       }
   };
 
@@ -87,12 +94,14 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
     if (rb < 3) load_z(rb + 1, nxt);  // next row block in flight while this one computes
     if (ka > 0) {
       const int row = wr0 + 16 * rb + li;
+      const int rowc = min(row, nrows - 1);
       for (int ks = 0; ks < nks; ++ks) {
         const int kk = 4 * ks + lq;
-        const TZ a = (row < nrows && kk < ka) ? -(TZ)A1[row0 + row + (int64_t)kk * lda] : TZ(0);
+        const TZ av = -(TZ)A1[row0 + rowc + (int64_t)min(kk, ka - 1) * lda];
+        const TZ a = (row < nrows && kk < ka) ? av : TZ(0);
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
-          if (cb < ncb) acc[cb] = M::mma(a, Ws[kk * 64 + 16 * cb + li], acc[cb]);
+          acc[cb] = M::mma(a, Ws[kk * 64 + 16 * cb + li], acc[cb]);
       }
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
@@ -112,13 +121,14 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
           const int kr = 16 * mb + li;
-          bo[mb] = (rr < nrows && kr < kb) ? (TZ)B1[row0 + rr + (int64_t)(kc0 + kr) * ldb] : TZ(0);
+          const TZ bv = (TZ)B1[row0 + min(rr, nrows - 1) + (int64_t)(kc0 + min(kr, kb - 1)) * ldb];
+          bo[mb] = (rr < nrows && kr < kb) ? bv : TZ(0);
         }
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
           for (int cb = 0; cb < 4; ++cb)
-            if (cb < ncb) pacc[mb][cb] = M::mma(bo[mb], acc[cb][t], pacc[mb][cb]);
+            pacc[mb][cb] = M::mma(bo[mb], acc[cb][t], pacc[mb][cb]);
       }
     }
   }
@@ -136,7 +146,7 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
           red[(w * kRows + kr) * 64 + 16 * cb + li] = pacc[mb][cb][t];
         }
     __syncthreads();
-    TZ* Pt = P + tile * (int64_t)kb_total * nz;
+    TZ* Pt = P + (int64_t)tile * kb_total * nz;
     for (int e = tid; e < kb * 64; e += kLpThreads) {
       const int kr = e % kb, cw = e / kb;
       const int col = c0 + cw;
@@ -151,16 +161,238 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
   }
 }
 
+
+// Fast variant: every tile height, the column count nz and both inner
+// dimensions are multiples of 16, so no element needs a clamp or a mask; the
+// update is computed transposed (Z^T -= W^T A1^T) so that the 16 lanes of a
+// row group hold 16 consecutive rows of one column of Z: every load and
+// store of Z and A1 covers whole 128-byte lines, addressed as a lane-uniform
+// base (scalar registers) plus one 32-bit lane offset.  For the product the
+// updated block is turned around through a per-wave LDS buffer (the
+// contraction runs over rows, which MFMA takes on its 4-deep K side); B1 is
+// loaded coalesced and turned around the same way.
+constexpr int kZtLd = 17;  // padded row length of the per-wave 16 x 16 turn-around buffer
+
+template <typename TZ, typename SA, typename SB, int MB, int NKS>
+__global__ __launch_bounds__(kLpThreads, MB > 2 ? 2 : 3) void level_pass_fast_kernel(
+    const Tile* __restrict__ tiles, int zchunks, int bchunks, TZ* Z, int64_t ldz, int nz, const SA* __restrict__ A1,
+    int64_t lda, const TZ* __restrict__ W, int64_t w_ld, int64_t w_pstride, int node_shift,
+    const SB* __restrict__ B1, int64_t ldb, int kb_total, TZ* __restrict__ P) {
+  using M = Mfma<TZ>;
+  using V = typename M::V;
+  constexpr int ka = 4 * NKS;
+  constexpr int kb = 16 * MB;  // B1 columns of this chunk (kb_total is a multiple of 16)
+  constexpr int kBtLd = 16 * MB + 1;
+  constexpr int kWave = 16 * kZtLd + 16 * kBtLd;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TZ* Ws = reinterpret_cast<TZ*>(smem_raw);   // W chunk [ka][64]
+  TZ* red = reinterpret_cast<TZ*>(smem_raw);  // end of the product: [2][kb][64]
+
+  const int lid = (int)xcd_remap(blockIdx.x, gridDim.x);  // grid < 2^31: 32-bit index math
+  const int bchunk = lid % bchunks;
+  const int zchunk = (lid / bchunks) % zchunks;
+  const int tile = lid / (bchunks * zchunks);
+  const Tile tl = tiles[tile];
+  const int64_t row0 = tl.row0;
+  const int nrows = tl.nrows;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lq = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: addresses stay scalar
+  const int c0 = zchunk * 64;
+  const int ncb = min(4, (nz - c0) >> 4);
+  const int wr0 = 64 * w;
+  const int nrb = max(0, min(4, (nrows - wr0) >> 4));  // 16-row blocks of this wave
+  const int kc0 = bchunk * 64;
+  constexpr bool prod = MB > 0;
+  TZ* zt = Ws + 64 * ka + w * kWave;
+  TZ* bt = zt + 16 * kZtLd;
+
+  if (NKS > 0) {
+    const int nd = tl.node >> node_shift;
+    const TZ* Wn = W + (int64_t)(nd >> 1) * w_pstride + (int64_t)(nd & 1) * ka;
+    for (int e = tid; e < 64 * ka; e += kLpThreads) {
+      const int c = e % 64, k = e / 64;
+      Ws[e] = (c0 + c < nz) ? Wn[k + (int64_t)(c0 + c) * w_ld] : TZ(0);
+    }
+  }
+
+  const auto zr = buf_rsrc(Z + row0 + wr0 + (int64_t)c0 * ldz);
+  const auto ar = buf_rsrc(A1 + row0 + wr0);
+  const auto br = buf_rsrc(B1 + row0 + wr0 + (int64_t)kc0 * ldb);
+  const uint32_t zl = (uint32_t)(li + (int64_t)M::crow_l(lq) * ldz) * (uint32_t)sizeof(TZ);
+  const uint32_t al = (uint32_t)(li + (int64_t)lq * lda) * (uint32_t)sizeof(SA);
+  const uint32_t bl = (uint32_t)(li + (int64_t)lq * ldb) * (uint32_t)sizeof(SB);
+  // Z(16 rb + li, 16 cb + crow(lq, t)): register t of the Z^T accumulator block cb
+  // column blocks past the end of a short chunk re-read the last one (uniform clamp): the values are
+  // computed on but never stored, so no lane needs a mask or a branch
+  auto zso = [&](int cb, int t) -> uint32_t {
+    return (uint32_t)((int64_t)(16 * min(cb, ncb - 1) + M::crow_u(t)) * ldz * (int64_t)sizeof(TZ));
+  };
+  auto zvo = [&](int rb) -> uint32_t { return zl + 16u * (uint32_t)rb * (uint32_t)sizeof(TZ); };
+  auto load_z = [&](int rb, V (&dst)[4]) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) dst[cb][t] = Buf<TZ>::load(zr, zvo(rb), zso(cb, t));
+  };
+  // B operand of the update: -A1(16 rb + li, 4 ks + lq)
+  auto load_a = [&](int rb, TZ (&dst)[NKS > 0 ? NKS : 1]) {
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks)
+      dst[ks] = -(TZ)Buf<SA>::load(ar, al + 16u * (uint32_t)rb * (uint32_t)sizeof(SA),
+                                   (uint32_t)((int64_t)(4 * ks) * lda * (int64_t)sizeof(SA)));
+  };
+  // B1(16 rb + li, kc0 + 4 i + lq)
+  auto load_b = [&](int rb, TZ (&dst)[MB > 0 ? 4 * MB : 1]) {
+#pragma unroll
+    for (int i = 0; i < 4 * MB; ++i)
+      dst[i] = (TZ)Buf<SB>::load(br, bl + 16u * (uint32_t)rb * (uint32_t)sizeof(SB),
+                                 (uint32_t)((int64_t)(4 * i) * ldb * (int64_t)sizeof(SB)));
+  };
+
+  V pacc[MB > 0 ? MB : 1][4];
+#pragma unroll
+  for (int mb = 0; mb < (MB > 0 ? MB : 1); ++mb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) pacc[mb][cb] = vzero<V>();
+
+  if (NKS > 0) __syncthreads();  // W chunk staged
+  // no software prefetch: latency is hidden by the other resident waves
+#pragma unroll 1
+  for (int rb = 0; rb < nrb; ++rb) {
+    V acc[4];
+    TZ acur[NKS > 0 ? NKS : 1];
+    TZ bcur[MB > 0 ? 4 * MB : 1];
+    // opaque per row block: keeps the W operands from being hoisted out of the loop (they would stay live)
+    int wso = lq * 64 + li;
+    asm volatile("" : "+v"(wso));
+    load_z(rb, acc);
+    if (NKS > 0) load_a(rb, acur);
+    if (prod) {
+      load_b(rb, bcur);
+#pragma unroll
+      for (int i = 0; i < 4 * MB; ++i) bt[li * kBtLd + 4 * i + lq] = bcur[i];
+    }
+    if (NKS > 0) {
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          acc[cb] = M::mma(Ws[wso + 4 * ks * 64 + 16 * cb], acur[ks], acc[cb]);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        if (cb < ncb) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) Buf<TZ>::store(acc[cb][t], zr, zvo(rb), zso(cb, t));
+        }
+    }
+    if (prod) {
+      // P(j, c) += sum_r B1(r, j) Z(r, c); K-step kk takes rows 4 kk + lq
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) zt[li * kZtLd + M::crow(lq, t)] = acc[cb][t];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const TZ zv = zt[(4 * kk + lq) * kZtLd + li];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+            pacc[mb][cb] = M::mma(bt[(4 * kk + lq) * kBtLd + 16 * mb + li], zv, pacc[mb][cb]);
+        }
+      }
+    }
+  }
+
+  if (prod) {
+    // partial products of the four waves, summed in the fixed order (w0 + w2) + (w1 + w3)
+    // through a two-slot LDS buffer that reuses the W chunk and turn-around space
+    __syncthreads();
+    if (w < 2) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) red[(w * kb + 16 * mb + M::crow(lq, t)) * 64 + 16 * cb + li] = pacc[mb][cb][t];
+    }
+    __syncthreads();
+    if (w >= 2) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            TZ* r = red + ((w - 2) * kb + 16 * mb + M::crow(lq, t)) * 64 + 16 * cb + li;
+            *r = *r + pacc[mb][cb][t];
+          }
+    }
+    __syncthreads();
+    TZ* Pt = P + (int64_t)tile * kb_total * nz;
+    for (int e = tid; e < kb * 64; e += kLpThreads) {
+      const int kr = e % kb, cw = e / kb;
+      const int col = c0 + cw;
+      if (col < nz) Pt[(kc0 + kr) + (int64_t)col * kb_total] = red[kr * 64 + cw] + red[(kb + kr) * 64 + cw];
+    }
+  }
+}
+
+template <typename TZ, typename SA, typename SB, int MB, int NKS>
+static hipError_t launch_fast(hipStream_t s, unsigned grid, int zchunks, int bchunks, const Tile* tiles, TZ* Z,
+                              int64_t ldz, int nz, const SA* A1, int64_t lda, const TZ* W, int64_t w_ld,
+                              int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P) {
+  auto k = level_pass_fast_kernel<TZ, SA, SB, MB, NKS>;
+  const size_t smem_main = sizeof(TZ) * (64 * 4 * (size_t)NKS + 4 * (16 * kZtLd + 16 * (16 * MB + 1)));
+  const size_t smem_red = MB > 0 ? sizeof(TZ) * 2 * 16 * MB * 64 : 0;
+  const size_t smem = smem_main > smem_red ? smem_main : smem_red;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kLpThreads), smem, s, tiles, zchunks, bchunks, Z, ldz, nz, A1, lda, W, w_ld,
+                     w_pstride, node_shift, B1, ldb, kb, P);
+  return hipGetLastError();
+}
+
+template <typename TZ, typename SA, typename SB, int MB>
+static hipError_t launch_fast_nks(int nks, hipStream_t s, unsigned grid, int zchunks, int bchunks, const Tile* tiles,
+                                  TZ* Z, int64_t ldz, int nz, const SA* A1, int64_t lda, const TZ* W, int64_t w_ld,
+                                  int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P) {
+#define HODLR_LPF(NKSV) \
+  return launch_fast<TZ, SA, SB, MB, NKSV>(s, grid, zchunks, bchunks, tiles, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, \
+                                            node_shift, B1, ldb, kb, P)
+  switch (nks) {
+    case 0: HODLR_LPF(0);
+    case 4: HODLR_LPF(4);
+    case 8: HODLR_LPF(8);
+    case 12: HODLR_LPF(12);
+    default: HODLR_LPF(16);
+  }
+#undef HODLR_LPF
+}
+
 template <typename TZ, typename SA, typename SB>
-hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, TZ* Z, int64_t ldz, int nz,
-                             const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld, int64_t w_pstride,
-                             int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P) {
+hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int tiles_aligned, TZ* Z, int64_t ldz,
+                             int nz, const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld,
+                             int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P) {
   if (ntiles == 0 || nz == 0 || (ka == 0 && kb == 0)) return hipSuccess;
   const int zchunks = (nz + 63) / 64;
   const int bchunks = kb > 0 ? (kb + 63) / 64 : 1;
   if (ka > 0 && bchunks > 1) return hipErrorInvalidValue;  // an update must run once per element
+  if (ka > 64) return hipErrorInvalidValue;
   const int64_t grid = (int64_t)ntiles * zchunks * bchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  // byte offsets inside a tile and chunk must stay below 2^31 for the buffer addressing
+  const bool small_ld = 64 * ldz * (int64_t)sizeof(TZ) < (1ll << 31) && 64 * lda * (int64_t)sizeof(SA) < (1ll << 31) &&
+                        64 * ldb * (int64_t)sizeof(SB) < (1ll << 31);
+  if (tiles_aligned && small_ld && nz % 16 == 0 && ka % 16 == 0 && kb % 16 == 0) {
+    const int nks = ka / 4;
+    switch (kb > 0 ? std::min(kb, 64) / 16 : 0) {
+      case 0: return launch_fast_nks<TZ, SA, SB, 0>(nks, s, (unsigned)grid, zchunks, bchunks, tiles, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);
+      case 1: return launch_fast_nks<TZ, SA, SB, 1>(nks, s, (unsigned)grid, zchunks, bchunks, tiles, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);
+      case 2: return launch_fast_nks<TZ, SA, SB, 2>(nks, s, (unsigned)grid, zchunks, bchunks, tiles, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);
+      case 3: return launch_fast_nks<TZ, SA, SB, 3>(nks, s, (unsigned)grid, zchunks, bchunks, tiles, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);
+      default: return launch_fast_nks<TZ, SA, SB, 4>(nks, s, (unsigned)grid, zchunks, bchunks, tiles, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);
+    }
+  }
   const int mbn = kb > 0 ? (min(kb, 64) + 15) / 16 : 1;
   const size_t smem_red = kb > 0 ? sizeof(TZ) * 4 * 16 * mbn * 64 : 0;
   const size_t smem_w = ka > 0 ? sizeof(TZ) * 64 * (size_t)((ka + 3) / 4 * 4) : 0;
@@ -184,7 +416,7 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, TZ* Z
 }
 
 #define HODLR_LP_INST(TZ, SA, SB)                                                                             \
-  template hipError_t launch_level_pass<TZ, SA, SB>(hipStream_t, int, const Tile*, TZ*, int64_t, int, const SA*, \
+  template hipError_t launch_level_pass<TZ, SA, SB>(hipStream_t, int, const Tile*, int, TZ*, int64_t, int, const SA*, \
                                                     int64_t, int, const TZ*, int64_t, int64_t, int,           \
                                                     const SB*, int64_t, int, TZ*);
 HODLR_LP_INST(double, double, double)

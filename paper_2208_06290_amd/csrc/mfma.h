@@ -22,6 +22,9 @@ struct Mfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int crow(int lq, int t) { return 4 * t + lq; }
+  // crow split into a lane-uniform part (by t) and a per-lane part (by lq)
+  static __device__ __forceinline__ constexpr int crow_u(int t) { return 4 * t; }
+  static __device__ __forceinline__ int crow_l(int lq) { return lq; }
 };
 template <>
 struct Mfma<float> {
@@ -30,6 +33,36 @@ struct Mfma<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int crow(int lq, int t) { return 4 * lq + t; }
+  static __device__ __forceinline__ constexpr int crow_u(int t) { return t; }
+  static __device__ __forceinline__ int crow_l(int lq) { return 4 * lq; }
+};
+
+// Raw buffer access: a lane-uniform base in a buffer resource (scalar
+// registers), a 32-bit per-lane offset and a 32-bit lane-uniform offset.
+// Offsets are in bytes; callers keep every offset below 2^31.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, -1, 0x00020000);
+}
+template <typename T>
+struct Buf;
+template <>
+struct Buf<double> {
+  static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, 0));
+  }
+  static __device__ __forceinline__ void store(double x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    using U = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, x), r, (int)v, (int)s, 0);
+  }
+};
+template <>
+struct Buf<float> {
+  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)v, (int)s, 0));
+  }
+  static __device__ __forceinline__ void store(float x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, (int)v, (int)s, 0);
+  }
 };
 
 template <typename V>
