@@ -12,8 +12,8 @@
 // 64w..64w+63), one chunk of 64 columns of Z and one chunk of <= 64 columns
 // of B1; the four waves' partial products are summed in LDS in a fixed order.
 //
-// Two kernels: level_pass_fast_kernel when tile heights, nz, ka and kb are
-// all multiples of 16 (the common case), level_pass_kernel otherwise.
+// Two kernels: level_pass_fast_kernel when tile heights, ka and kb are
+// multiples of 16 (the common case), level_pass_kernel otherwise.
 #include "mfma.h"
 
 #include <algorithm>
@@ -162,31 +162,35 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
 }
 
 
-// Fast variant: every tile height, the column count nz and both inner
-// dimensions are multiples of 16, so no element needs a clamp or a mask; the
-// update is computed transposed (Z^T -= W^T A1^T) so that the 16 lanes of a
-// row group hold 16 consecutive rows of one column of Z: every load and
-// store of Z and A1 covers whole 128-byte lines, addressed as a lane-uniform
-// base (scalar registers) plus one 32-bit lane offset.  For the product the
+// Fast kernel: tile heights, ka and kb are multiples of 16 (nz is free).  The
+// update is computed transposed, Z^T -= W^T A1^T, so that the 16 lanes of a
+// row group hold 16 consecutive rows of one column of Z: every load and store
+// of Z and A1 covers whole 128-byte lines, addressed as a lane-uniform base
+// plus one 32-bit lane offset (buffer addressing).  For the product the
 // updated block is turned around through a per-wave LDS buffer (the
 // contraction runs over rows, which MFMA takes on its 4-deep K side); B1 is
-// loaded coalesced and turned around the same way.
+// loaded coalesced and turned around the same way.  A chunk is 16 NCB
+// columns of Z (NCB = 1 for narrow right-hand sides, else 4).  Columns past
+// nz are computed on zeros and never stored; their loads are redirected to an
+// in-range column, so no access leaves the operands.
 constexpr int kZtLd = 17;  // padded row length of the per-wave 16 x 16 turn-around buffer
 
-template <typename TZ, typename SA, typename SB, int MB, int NKS>
-__global__ __launch_bounds__(kLpThreads, MB > 2 ? 2 : 3) void level_pass_fast_kernel(
-    const Tile* __restrict__ tiles, int zchunks, int bchunks, TZ* Z, int64_t ldz, int nz, const SA* __restrict__ A1,
+template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE>
+__global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level_pass_fast_kernel(
+    const Tile* __restrict__ tiles, int zchunks, int zc_base, int bchunks, TZ* Z, int64_t ldz, int nz, const SA* __restrict__ A1,
     int64_t lda, const TZ* __restrict__ W, int64_t w_ld, int64_t w_pstride, int node_shift,
     const SB* __restrict__ B1, int64_t ldb, int kb_total, TZ* __restrict__ P) {
   using M = Mfma<TZ>;
   using V = typename M::V;
   constexpr int ka = 4 * NKS;
   constexpr int kb = 16 * MB;  // B1 columns of this chunk (kb_total is a multiple of 16)
+  constexpr int kCw = 16 * NCB;  // Z columns of a chunk
   constexpr int kBtLd = 16 * MB + 1;
   constexpr int kWave = 16 * kZtLd + 16 * kBtLd;
+  constexpr bool prod = MB > 0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  TZ* Ws = reinterpret_cast<TZ*>(smem_raw);   // W chunk [ka][64]
-  TZ* red = reinterpret_cast<TZ*>(smem_raw);  // end of the product: [2][kb][64]
+  TZ* Ws = reinterpret_cast<TZ*>(smem_raw);   // W chunk [ka][kCw]
+  TZ* red = reinterpret_cast<TZ*>(smem_raw);  // end of the product: [2][kb][kCw]
 
   const int lid = (int)xcd_remap(blockIdx.x, gridDim.x);  // grid < 2^31: 32-bit index math
   const int bchunk = lid % bchunks;
@@ -197,42 +201,59 @@ __global__ __launch_bounds__(kLpThreads, MB > 2 ? 2 : 3) void level_pass_fast_ke
   const int nrows = tl.nrows;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lq = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: addresses stay scalar
-  const int c0 = zchunk * 64;
-  const int ncb = min(4, (nz - c0) >> 4);
+  const int c0 = (zc_base + zchunk) * kCw;
+  const int ncz = MODE == 0 ? kCw : min(kCw, nz - c0);  // valid columns of this chunk
   const int wr0 = 64 * w;
   const int nrb = max(0, min(4, (nrows - wr0) >> 4));  // 16-row blocks of this wave
   const int kc0 = bchunk * 64;
-  constexpr bool prod = MB > 0;
-  TZ* zt = Ws + 64 * ka + w * kWave;
+  TZ* zt = Ws + kCw * ka + w * kWave;
   TZ* bt = zt + 16 * kZtLd;
 
   if (NKS > 0) {
     const int nd = tl.node >> node_shift;
     const TZ* Wn = W + (int64_t)(nd >> 1) * w_pstride + (int64_t)(nd & 1) * ka;
-    for (int e = tid; e < 64 * ka; e += kLpThreads) {
-      const int c = e % 64, k = e / 64;
-      Ws[e] = (c0 + c < nz) ? Wn[k + (int64_t)(c0 + c) * w_ld] : TZ(0);
+    for (int e = tid; e < kCw * ka; e += kLpThreads) {
+      const int c = e % kCw, k = e / kCw;
+      Ws[e] = (c < ncz) ? Wn[k + (int64_t)(c0 + c) * w_ld] : TZ(0);
     }
   }
 
   const auto zr = buf_rsrc(Z + row0 + wr0 + (int64_t)c0 * ldz);
-  const auto ar = buf_rsrc(A1 + row0 + wr0);
-  const auto br = buf_rsrc(B1 + row0 + wr0 + (int64_t)kc0 * ldb);
-  const uint32_t zl = (uint32_t)(li + (int64_t)M::crow_l(lq) * ldz) * (uint32_t)sizeof(TZ);
+  const auto ar = buf_rsrc(NKS > 0 ? A1 + row0 + wr0 : A1);  // A1 / B1 are null when unused
+  const auto br = buf_rsrc(prod ? B1 + row0 + wr0 + (int64_t)kc0 * ldb : B1);
+  const uint32_t zrow = (uint32_t)li * (uint32_t)sizeof(TZ);
+  const uint32_t zl = zrow + (uint32_t)((int64_t)M::crow_l(lq) * ldz) * (uint32_t)sizeof(TZ);
   const uint32_t al = (uint32_t)(li + (int64_t)lq * lda) * (uint32_t)sizeof(SA);
   const uint32_t bl = (uint32_t)(li + (int64_t)lq * ldb) * (uint32_t)sizeof(SB);
-  // Z(16 rb + li, 16 cb + crow(lq, t)): register t of the Z^T accumulator block cb
-  // column blocks past the end of a short chunk re-read the last one (uniform clamp): the values are
-  // computed on but never stored, so no lane needs a mask or a branch
-  auto zso = [&](int cb, int t) -> uint32_t {
-    return (uint32_t)((int64_t)(16 * min(cb, ncb - 1) + M::crow_u(t)) * ldz * (int64_t)sizeof(TZ));
+  // Z(16 rb + li, c0 + 16 cb + crow(lq, t)) is register t of the Z^T accumulator
+  // block cb.  The lane-uniform column part is clamped into the chunk; a lane
+  // whose own column is past nz drops its lane part and reads the clamped
+  // column instead (its value is replaced by zero).
+  // MODE 0: every column of the chunk is valid; MODE 1: the valid columns
+  // are whole 16-column blocks (later blocks re-read the last valid one, a
+  // lane-uniform clamp); MODE 2: any count (per-lane test)
+  auto zok = [&](int cb, int t) -> bool {
+    if (MODE == 0) return true;
+    if (MODE == 1) return 16 * cb < ncz;
+    return 16 * cb + M::crow_u(t) + M::crow_l(lq) < ncz;
   };
-  auto zvo = [&](int rb) -> uint32_t { return zl + 16u * (uint32_t)rb * (uint32_t)sizeof(TZ); };
-  auto load_z = [&](int rb, V (&dst)[4]) {
+  auto zso = [&](int cb, int t) -> uint32_t {
+    const int col = MODE == 0   ? 16 * cb + M::crow_u(t)
+                    : MODE == 1 ? 16 * min(cb, (ncz >> 4) - 1) + M::crow_u(t)
+                                : min(16 * cb + M::crow_u(t), ncz - 1);
+    return (uint32_t)((int64_t)col * ldz * (int64_t)sizeof(TZ));
+  };
+  auto zvo = [&](int rb, int cb, int t) -> uint32_t {
+    return (MODE < 2 || zok(cb, t) ? zl : zrow) + 16u * (uint32_t)rb * (uint32_t)sizeof(TZ);
+  };
+  auto load_z = [&](int rb, V (&dst)[NCB]) {
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) dst[cb][t] = Buf<TZ>::load(zr, zvo(rb), zso(cb, t));
+      for (int t = 0; t < 4; ++t) {
+        const TZ v = Buf<TZ>::load(zr, zvo(rb, cb, t), zso(cb, t));
+        dst[cb][t] = zok(cb, t) ? v : TZ(0);
+      }
   };
   // B operand of the update: -A1(16 rb + li, 4 ks + lq)
   auto load_a = [&](int rb, TZ (&dst)[NKS > 0 ? NKS : 1]) {
@@ -241,30 +262,32 @@ __global__ __launch_bounds__(kLpThreads, MB > 2 ? 2 : 3) void level_pass_fast_ke
       dst[ks] = -(TZ)Buf<SA>::load(ar, al + 16u * (uint32_t)rb * (uint32_t)sizeof(SA),
                                    (uint32_t)((int64_t)(4 * ks) * lda * (int64_t)sizeof(SA)));
   };
-  // B1(16 rb + li, kc0 + 4 i + lq)
+  // B1(16 rb + li, kc0 + 4 i + lq); the last B1 chunk may hold fewer than kb
+  // columns (a multiple of 16): the others read column kc0 and are zeroed
+  const int kbc = prod ? min(kb, kb_total - kc0) : 0;
   auto load_b = [&](int rb, TZ (&dst)[MB > 0 ? 4 * MB : 1]) {
 #pragma unroll
-    for (int i = 0; i < 4 * MB; ++i)
-      dst[i] = (TZ)Buf<SB>::load(br, bl + 16u * (uint32_t)rb * (uint32_t)sizeof(SB),
-                                 (uint32_t)((int64_t)(4 * i) * ldb * (int64_t)sizeof(SB)));
+    for (int i = 0; i < 4 * MB; ++i) {
+      const bool ok = 4 * i < kbc;  // uniform
+      const TZ v = (TZ)Buf<SB>::load(br, bl + 16u * (uint32_t)rb * (uint32_t)sizeof(SB),
+                                     (uint32_t)((int64_t)(ok ? 4 * i : 0) * ldb * (int64_t)sizeof(SB)));
+      dst[i] = ok ? v : TZ(0);
+    }
   };
 
-  V pacc[MB > 0 ? MB : 1][4];
+  V pacc[MB > 0 ? MB : 1][NCB];
 #pragma unroll
   for (int mb = 0; mb < (MB > 0 ? MB : 1); ++mb)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) pacc[mb][cb] = vzero<V>();
+    for (int cb = 0; cb < NCB; ++cb) pacc[mb][cb] = vzero<V>();
 
   if (NKS > 0) __syncthreads();  // W chunk staged
   // no software prefetch: latency is hidden by the other resident waves
 #pragma unroll 1
   for (int rb = 0; rb < nrb; ++rb) {
-    V acc[4];
+    V acc[NCB];
     TZ acur[NKS > 0 ? NKS : 1];
     TZ bcur[MB > 0 ? 4 * MB : 1];
-    // opaque per row block: keeps the W operands from being hoisted out of the loop (they would stay live)
-    int wso = lq * 64 + li;
-    asm volatile("" : "+v"(wso));
     load_z(rb, acc);
     if (NKS > 0) load_a(rb, acur);
     if (prod) {
@@ -274,22 +297,20 @@ __global__ __launch_bounds__(kLpThreads, MB > 2 ? 2 : 3) void level_pass_fast_ke
     }
     if (NKS > 0) {
 #pragma unroll
-      for (int ks = 0; ks < NKS; ++ks) {
+      for (int ks = 0; ks < NKS; ++ks)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-          acc[cb] = M::mma(Ws[wso + 4 * ks * 64 + 16 * cb], acur[ks], acc[cb]);
-      }
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[cb] = M::mma(Ws[(4 * ks + lq) * kCw + 16 * cb + li], acur[ks], acc[cb]);
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
-        if (cb < ncb) {
+      for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-          for (int t = 0; t < 4; ++t) Buf<TZ>::store(acc[cb][t], zr, zvo(rb), zso(cb, t));
-        }
+        for (int t = 0; t < 4; ++t)
+          if (zok(cb, t)) Buf<TZ>::store(acc[cb][t], zr, zvo(rb, cb, t), zso(cb, t));
     }
     if (prod) {
       // P(j, c) += sum_r B1(r, j) Z(r, c); K-step kk takes rows 4 kk + lq
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
+      for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) zt[li * kZtLd + M::crow(lq, t)] = acc[cb][t];
 #pragma unroll
@@ -311,54 +332,68 @@ __global__ __launch_bounds__(kLpThreads, MB > 2 ? 2 : 3) void level_pass_fast_ke
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-          for (int t = 0; t < 4; ++t) red[(w * kb + 16 * mb + M::crow(lq, t)) * 64 + 16 * cb + li] = pacc[mb][cb][t];
+          for (int t = 0; t < 4; ++t)
+            red[(w * kb + 16 * mb + M::crow(lq, t)) * kCw + 16 * cb + li] = pacc[mb][cb][t];
     }
     __syncthreads();
     if (w >= 2) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            TZ* r = red + ((w - 2) * kb + 16 * mb + M::crow(lq, t)) * 64 + 16 * cb + li;
+            TZ* r = red + ((w - 2) * kb + 16 * mb + M::crow(lq, t)) * kCw + 16 * cb + li;
             *r = *r + pacc[mb][cb][t];
           }
     }
     __syncthreads();
     TZ* Pt = P + (int64_t)tile * kb_total * nz;
-    for (int e = tid; e < kb * 64; e += kLpThreads) {
+    for (int e = tid; e < kb * kCw; e += kLpThreads) {
       const int kr = e % kb, cw = e / kb;
-      const int col = c0 + cw;
-      if (col < nz) Pt[(kc0 + kr) + (int64_t)col * kb_total] = red[kr * 64 + cw] + red[(kb + kr) * 64 + cw];
+      if (cw < ncz && kr < kbc)
+        Pt[(kc0 + kr) + (int64_t)(c0 + cw) * kb_total] = red[kr * kCw + cw] + red[(kb + kr) * kCw + cw];
     }
   }
 }
 
-template <typename TZ, typename SA, typename SB, int MB, int NKS>
-static hipError_t launch_fast(hipStream_t s, unsigned grid, int zchunks, int bchunks, const Tile* tiles, TZ* Z,
-                              int64_t ldz, int nz, const SA* A1, int64_t lda, const TZ* W, int64_t w_ld,
-                              int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P) {
-  auto k = level_pass_fast_kernel<TZ, SA, SB, MB, NKS>;
-  const size_t smem_main = sizeof(TZ) * (64 * 4 * (size_t)NKS + 4 * (16 * kZtLd + 16 * (16 * MB + 1)));
-  const size_t smem_red = MB > 0 ? sizeof(TZ) * 2 * 16 * MB * 64 : 0;
+template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB>
+static hipError_t launch_fast(hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z, int64_t ldz,
+                              const SA* A1, int64_t lda, const TZ* W, int64_t w_ld, int64_t w_pstride,
+                              int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P) {
+  constexpr int kCw = 16 * NCB;
+  const size_t smem_main = sizeof(TZ) * (kCw * 4 * (size_t)NKS + 4 * (16 * kZtLd + 16 * (16 * MB + 1)));
+  const size_t smem_red = MB > 0 ? sizeof(TZ) * 2 * 16 * MB * kCw : 0;
   const size_t smem = smem_main > smem_red ? smem_main : smem_red;
-  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(kLpThreads), smem, s, tiles, zchunks, bchunks, Z, ldz, nz, A1, lda, W, w_ld,
-                     w_pstride, node_shift, B1, ldb, kb, P);
-  return hipGetLastError();
+  // whole chunks in one launch, the ragged last chunk (if any) in a second
+  const int nfull = nz / kCw, rest = nz % kCw;
+  for (int part = 0; part < 2; ++part) {
+    const int zchunks = part == 0 ? nfull : (rest ? 1 : 0);
+    if (zchunks == 0) continue;
+    const int64_t grid = (int64_t)ntiles * zchunks * bchunks;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    auto k = part == 0 ? level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, 0>
+             : rest % 16 == 0 ? level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, 1>
+                              : level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, 2>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kLpThreads), smem, s, tiles, zchunks, part == 0 ? 0 : nfull,
+                       bchunks, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
-template <typename TZ, typename SA, typename SB, int MB>
-static hipError_t launch_fast_nks(int nks, hipStream_t s, unsigned grid, int zchunks, int bchunks, const Tile* tiles,
-                                  TZ* Z, int64_t ldz, int nz, const SA* A1, int64_t lda, const TZ* W, int64_t w_ld,
+template <typename TZ, typename SA, typename SB, int MB, int NCB>
+static hipError_t launch_fast_nks(int nks, hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z,
+                                  int64_t ldz, const SA* A1, int64_t lda, const TZ* W, int64_t w_ld,
                                   int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P) {
-#define HODLR_LPF(NKSV) \
-  return launch_fast<TZ, SA, SB, MB, NKSV>(s, grid, zchunks, bchunks, tiles, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, \
-                                            node_shift, B1, ldb, kb, P)
+#define HODLR_LPF(NKSV)                                                                                       \
+  return launch_fast<TZ, SA, SB, MB, NKSV, NCB>(s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld, w_pstride, \
+                                                 node_shift, B1, ldb, kb, P)
   switch (nks) {
     case 0: HODLR_LPF(0);
     case 4: HODLR_LPF(4);
@@ -367,6 +402,25 @@ static hipError_t launch_fast_nks(int nks, hipStream_t s, unsigned grid, int zch
     default: HODLR_LPF(16);
   }
 #undef HODLR_LPF
+}
+
+template <typename TZ, typename SA, typename SB, int NCB>
+static hipError_t launch_fast_all(hipStream_t s, int ntiles, const Tile* tiles, TZ* Z, int64_t ldz, int nz,
+                                  const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld, int64_t w_pstride,
+                                  int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P) {
+  const int bchunks = kb > 0 ? (kb + 63) / 64 : 1;
+  const int nks = ka / 4;
+#define HODLR_LPM(MBV)                                                                                            \
+  return launch_fast_nks<TZ, SA, SB, MBV, NCB>(nks, s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,      \
+                                                w_pstride, node_shift, B1, ldb, kb, P)
+  switch (kb > 0 ? std::min(kb, 64) / 16 : 0) {
+    case 0: HODLR_LPM(0);
+    case 1: HODLR_LPM(1);
+    case 2: HODLR_LPM(2);
+    case 3: HODLR_LPM(3);
+    default: HODLR_LPM(4);
+  }
+#undef HODLR_LPM
 }
 
 template <typename TZ, typename SA, typename SB>
@@ -383,15 +437,12 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int t
   // byte offsets inside a tile and chunk must stay below 2^31 for the buffer addressing
   const bool small_ld = 64 * ldz * (int64_t)sizeof(TZ) < (1ll << 31) && 64 * lda * (int64_t)sizeof(SA) < (1ll << 31) &&
                         64 * ldb * (int64_t)sizeof(SB) < (1ll << 31);
-  if (tiles_aligned && small_ld && nz % 16 == 0 && ka % 16 == 0 && kb % 16 == 0) {
-    const int nks = ka / 4;
-    switch (kb > 0 ? std::min(kb, 64) / 16 : 0) {
-      case 0: return launch_fast_nks<TZ, SA, SB, 0>(nks, s, (unsigned)grid, zchunks, bchunks, tiles, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);
-      case 1: return launch_fast_nks<TZ, SA, SB, 1>(nks, s, (unsigned)grid, zchunks, bchunks, tiles, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);
-      case 2: return launch_fast_nks<TZ, SA, SB, 2>(nks, s, (unsigned)grid, zchunks, bchunks, tiles, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);
-      case 3: return launch_fast_nks<TZ, SA, SB, 3>(nks, s, (unsigned)grid, zchunks, bchunks, tiles, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);
-      default: return launch_fast_nks<TZ, SA, SB, 4>(nks, s, (unsigned)grid, zchunks, bchunks, tiles, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);
-    }
+  if (tiles_aligned && small_ld && ka % 16 == 0 && kb % 16 == 0) {
+    if (nz <= 16)
+      return launch_fast_all<TZ, SA, SB, 1>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride, node_shift,
+                                            B1, ldb, kb, P);
+    return launch_fast_all<TZ, SA, SB, 4>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride, node_shift,
+                                          B1, ldb, kb, P);
   }
   const int mbn = kb > 0 ? (min(kb, 64) + 15) / 16 : 1;
   const size_t smem_red = kb > 0 ? sizeof(TZ) * 4 * 16 * mbn * 64 : 0;
