@@ -16,7 +16,8 @@ plus one solve of the right-hand side.  Reported:
              the MI355X peak
   cpu_baseline  the CPU oracle on a bounded sample of the same workload
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu] [--no-mixed]
+       python bench.py --copy-probe     (plain device copy, for counter calibration)
 """
 import argparse
 import json
@@ -83,6 +84,11 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override N (same leaf and rank)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 + refinement path")
+    ap.add_argument("--synthetic", action="store_true",
+                    help="random generators of the same N, leaf and rank instead of the BIE matrix (same shapes, "
+                         "so the same kernels and traffic; used for counter runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -97,8 +103,20 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        _say("copy probe: 3 copies of 1 GiB (read 1 GiB + write 1 GiB each)")
+        return
     t0 = time.time()
-    inp = W.make_config(2, device=dev, n=args.n)
+    if args.synthetic:
+        c2 = W.CONFIGS[2]
+        inp = W.synthetic(args.n or c2["n"], c2["leaf"], c2["rank"], seed=0, dtype=torch.float64, device=dev)
+    else:
+        inp = W.make_config(2, device=dev, n=args.n)
     torch.cuda.synchronize()
     _say(f"generated {inp.name} in {time.time() - t0:.1f}s")
     N = inp.n

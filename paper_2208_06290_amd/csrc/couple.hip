@@ -29,9 +29,15 @@ __global__ void segment_reduce_kernel(const int2* __restrict__ desc, int64_t ele
   const int sg = blockIdx.y;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= elems) return;
-  const int2 d = desc[sg];
-  T acc = T(0);
-  for (int t = 0; t < d.y; ++t) acc += P[(int64_t)(d.x + t) * elems + e];
+  const int2 d = desc[sg];  // d.y <= kSegTiles items
+  // all loads in flight at once (clamped to the segment), summed in item order
+  T v[kSegTiles];
+#pragma unroll
+  for (int t = 0; t < kSegTiles; ++t) v[t] = P[(int64_t)(d.x + min(t, d.y - 1)) * elems + e];
+  T acc = v[0];
+#pragma unroll
+  for (int t = 1; t < kSegTiles; ++t)
+    if (t < d.y) acc += v[t];
   out[(int64_t)sg * elems + e] = acc;
 }
 
@@ -154,6 +160,92 @@ __device__ __forceinline__ void wave_lu_solve(T (&x)[2][NC], const T* Kf, const 
 // ---------------------------------------------------------------------------
 constexpr int kCfThreads = 256;
 
+// LU with partial pivoting of the n2 x n2 (n2 <= 64) matrix K (LDS, col-major)
+// by the four waves of the workgroup with the matrix in registers: lane i
+// holds row i, wave w columns 16w .. 16w+15.  Rows are not moved while
+// factoring; each lane tracks the position of its row.  At step j the wave
+// owning column j picks the largest |K(., j)| among unpivoted rows (lowest
+// position on ties, a NaN counts as infinite) and publishes the multipliers
+// through LDS (double buffered: one barrier per step); every wave then takes
+// the pivot row from its own registers with readlane and updates its columns.
+// The step loop is not unrolled (the code runs a few times per workgroup:
+// straight-line code would be bound by instruction fetch); column j is picked
+// out of the registers with selects, so register indices stay compile-time
+// constants.  On return K holds L\U in pivoted order and spiv[j] the
+// LAPACK-style interchange of step j.
+template <typename T>
+__device__ __forceinline__ void block_lu(T* K, int n2, int lane, int w, int* spiv, unsigned long long* info,
+                                         unsigned long long info_base) {
+  __shared__ T s_l[2][64];
+  __shared__ int s_pl[2][2];  // pivot lane, pivot value nonzero
+  T kc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int col = 16 * w + c;
+    kc[c] = (lane < n2 && col < n2) ? K[lane + col * n2] : T(0);
+  }
+  int mypos = lane;
+  bool done = lane >= n2;
+  for (int j = 0; j < n2; ++j) {
+    const int sb = j & 1;
+    if (w == (j >> 4)) {
+      const int jc = j & 15;
+      T kj = T(0);
+#pragma unroll
+      for (int c = 0; c < 16; ++c) kj = (c == jc) ? kc[c] : kj;
+      T v = done ? T(-1) : fabs(kj);
+      if (!done && !(v == v)) v = T(INFINITY);
+      int key = done ? 0x7fffffff : mypos;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const T ov = __shfl_xor(v, off, 64);
+        const int ok = __shfl_xor(key, off, 64);
+        if (ov > v || (ov == v && ok < key)) {
+          v = ov;
+          key = ok;
+        }
+      }
+      const int bk = __builtin_amdgcn_readfirstlane(key);  // pivot position (uniform)
+      const unsigned long long sel = __ballot(!done && mypos == bk);
+      const int plane = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(sel));
+      const T pv = bcast(kj, plane);
+      const bool nz = pv != T(0);
+      s_l[sb][lane] = (!done && lane != plane && nz) ? kj * (T(1) / pv) : T(0);
+      if (lane == 0) {
+        s_pl[sb][0] = plane;
+        s_pl[sb][1] = nz;
+        spiv[j] = bk;
+        if (!nz) atomicMin(info, info_base | (unsigned long long)j);
+      }
+    }
+    __syncthreads();
+    const int plane = __builtin_amdgcn_readfirstlane(s_pl[sb][0]);
+    const bool nz = s_pl[sb][1] != 0;
+    const T l = s_l[sb][lane];
+    const bool me = lane == plane;
+    const bool upd = !done && !me && nz;
+    const int bk = __builtin_amdgcn_readfirstlane(__shfl(mypos, plane, 64));
+    if (!done && !me && mypos == j) mypos = bk;  // the row displaced by the interchange
+    if (me) {
+      done = true;
+      mypos = j;
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int col = 16 * w + c;
+      const T pc = bcast(kc[c], plane);
+      const T nv = (col == j) ? l : kc[c] - l * pc;
+      kc[c] = (upd && col >= j) ? nv : kc[c];
+    }
+  }
+  __syncthreads();  // every wave has read K before it is overwritten
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int col = 16 * w + c;
+    if (lane < n2 && col < n2) K[mypos + col * n2] = kc[c];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp, int Rp, const T* __restrict__ segs,
                                                                    const int32_t* __restrict__ seg_start,
@@ -174,21 +266,31 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp
   const int64_t elems = (int64_t)r * ncin;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
+  // the children's products have been reduced to one item per node
+  const T* Pa = segs + (int64_t)seg_start[a] * elems;
+  const T* Pb = segs + (int64_t)seg_start[b] * elems;
+#pragma unroll 4
   for (int e = tid; e < n2 * n2; e += kCfThreads) {
     const int i = e % n2, j = e / n2;
-    T v;
-    if (i < r && j < r)
-      v = seg_sum(segs, seg_start, a, elems, i + (int64_t)(Rp + j) * r);
-    else if (i >= r && j >= r)
-      v = seg_sum(segs, seg_start, b, elems, (i - r) + (int64_t)(Rp + j - r) * r);
-    else if (i < r)
-      v = (j - r == i) ? T(1) : T(0);
-    else
-      v = (i - r == j) ? T(1) : T(0);
-    K[i + j * n2] = v;
+    const bool da = i < r && j < r, db = i >= r && j >= r;
+    const T va = Pa[min(i, r - 1) + (int64_t)(Rp + min(j, r - 1)) * r];
+    const T vb = Pb[max(i - r, 0) + (int64_t)(Rp + max(j - r, 0)) * r];
+    const T id = (i < r ? j - r == i : i - r == j) ? T(1) : T(0);
+    K[i + j * n2] = da ? va : (db ? vb : id);
   }
   __syncthreads();
-  if (wid == 0) {
+  // right-hand sides of eq. "e:node1", unpermuted (the block solver applies the pivots)
+  {
+    T* Wg = W + (int64_t)g * n2 * Rp;
+#pragma unroll 4
+    for (int e = tid; e < n2 * Rp; e += kCfThreads) {
+      const int i = e % n2, cc = e / n2;
+      Wg[e] = (i < r ? Pa : Pb)[(i % r) + (int64_t)cc * r];
+    }
+  }
+  if (n2 <= 64) {
+    block_lu(K, n2, lane, wid, spiv, info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16));
+  } else if (wid == 0) {
     // LU with partial pivoting by one wave (rows over lanes, no block barriers)
     for (int j = 0; j < n2; ++j) {
       T best = T(-1);
@@ -251,14 +353,6 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-  } else {
-    // right-hand sides of eq. "e:node1", unpermuted (the block solver applies the pivots)
-    T* Wg = W + (int64_t)g * n2 * Rp;
-    for (int64_t e = tid - 64; e < (int64_t)n2 * Rp; e += kCfThreads - 64) {
-      const int i = (int)(e % n2), cc = (int)(e / n2);
-      const int node = i < r ? a : b;
-      Wg[e] = seg_sum(segs, seg_start, node, elems, (i % r) + (int64_t)cc * r);
     }
   }
   __syncthreads();
@@ -387,10 +481,89 @@ __global__ __launch_bounds__(64) void couple_solve_kernel(int r, int kp, int nrh
   }
 }
 
+// Same solve for 2r <= 64 with the factor staged in LDS, lane i owning row i
+// of the right-hand sides: each substitution step reads one LDS entry per lane
+// (prefetched a step ahead) and broadcasts x_j with readlane.  The loops are
+// not unrolled: the code runs once per wave and would otherwise be bound by
+// instruction fetch.
+template <typename T, int TRANS>
+__global__ __launch_bounds__(64) void couple_solve_reg_kernel(int r, int kp, int nrhs, const T* __restrict__ segs,
+                                                              const int32_t* __restrict__ seg_start,
+                                                              const T* __restrict__ Klu,
+                                                              const int32_t* __restrict__ Kperm,
+                                                              const T* __restrict__ Kud, T* __restrict__ w) {
+  __shared__ T Ks[64 * 64];  // Ks[j * 64 + i] = K(i, j) (TRANS: K(j, i))
+  const int g = blockIdx.x;
+  const int a = 2 * g, b = 2 * g + 1;
+  const int n2 = 2 * r;
+  const int lane = threadIdx.x;
+  const int64_t elems = (int64_t)r * nrhs;
+  const T* Kf = Klu + (int64_t)g * kp * kp;
+  const int32_t* pm = Kperm + (int64_t)g * kp;
+  T* wg = w + (int64_t)g * n2 * nrhs;
+  const bool valid = lane < n2;
+  const int ln = valid ? lane : 0;
+  for (int j = 0; j < n2; ++j) Ks[j * 64 + lane] = TRANS ? Kf[j + (int64_t)ln * kp] : Kf[ln + (int64_t)j * kp];
+  const T dinv = valid ? Kud[(int64_t)g * kp + lane] : T(1);
+  const int src = TRANS ? ln : pm[ln];
+  const int64_t sbase = (int64_t)seg_start[src < r ? a : b] * elems + (src % r);
+  const int dst = TRANS ? pm[ln] : ln;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int c0 = 0; c0 < nrhs; c0 += kCsCols) {
+    T x[kCsCols];
+#pragma unroll
+    for (int c = 0; c < kCsCols; ++c) {
+      const T v = segs[sbase + (int64_t)min(c0 + c, nrhs - 1) * r];
+      x[c] = (valid && c0 + c < nrhs) ? v : T(0);
+    }
+    // forward: L (unit lower) or U^T (lower); backward: U or L^T (unit upper)
+    T f = Ks[lane];
+    for (int j = 0; j < n2; ++j) {
+      const T fj = f;
+      f = Ks[min(j + 1, 63) * 64 + lane];
+      const T dj = TRANS ? bcast(dinv, j) : T(1);
+#pragma unroll
+      for (int c = 0; c < kCsCols; ++c) {
+        const T xj = bcast(x[c], j) * dj;
+        if (TRANS && lane == j) x[c] = xj;
+        else if (lane > j) x[c] -= fj * xj;
+      }
+    }
+    f = Ks[(n2 - 1) * 64 + lane];
+    for (int j = n2 - 1; j >= 0; --j) {
+      const T fj = f;
+      f = Ks[max(j - 1, 0) * 64 + lane];
+      const T dj = TRANS ? T(1) : bcast(dinv, j);
+#pragma unroll
+      for (int c = 0; c < kCsCols; ++c) {
+        const T xj = bcast(x[c], j) * dj;
+        if (!TRANS && lane == j) x[c] = xj;
+        else if (lane < j) x[c] -= fj * xj;
+      }
+    }
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < kCsCols; ++c)
+        if (c0 + c < nrhs) wg[dst + (int64_t)(c0 + c) * n2] = x[c];
+    }
+  }
+}
+
 template <typename T>
 hipError_t launch_couple_solve(hipStream_t s, int trans, int nparents, int r, int kp, int nrhs, const T* segs,
                                const int32_t* d_seg_start, const T* Klu, const int32_t* Kperm, const T* Kud, T* w) {
   if (nparents == 0 || r == 0 || nrhs == 0) return hipSuccess;
+  if (2 * r <= 64) {
+    if (trans)
+      hipLaunchKernelGGL((couple_solve_reg_kernel<T, 1>), dim3(nparents), dim3(64), 0, s, r, kp, nrhs, segs,
+                         d_seg_start, Klu, Kperm, Kud, w);
+    else
+      hipLaunchKernelGGL((couple_solve_reg_kernel<T, 0>), dim3(nparents), dim3(64), 0, s, r, kp, nrhs, segs,
+                         d_seg_start, Klu, Kperm, Kud, w);
+    return hipGetLastError();
+  }
   if (trans)
     hipLaunchKernelGGL((couple_solve_kernel<T, 1>), dim3(nparents), dim3(64), 0, s, r, kp, nrhs, segs, d_seg_start,
                        Klu, Kperm, Kud, w);

@@ -122,7 +122,7 @@ struct DevMem {
 
 // Reduction plan of a product whose node level is p, computed on tiles of level q >= p.
 // Tile partials are summed in stages of at most kSegTiles items (fixed order) until every
-// node has at most kSegTiles partial sums left; the coupling kernels add those.
+// node has a single sum left, which the coupling kernels read.
 struct ProdStage {
   int nsegs = 0;
   int2* d_desc = nullptr;  // per output segment: first input item, count
@@ -265,7 +265,7 @@ hodlr_status make_prod(hodlr_factors* F, int q, int p, hipStream_t st) {
   while (true) {
     int mx = 0;
     for (int i = 0; i < pp.nnodes; ++i) mx = std::max(mx, start[i + 1] - start[i]);
-    if (mx <= kSegTiles) break;
+    if (mx <= 1) break;  // reduced to one item per node: the coupling kernels read plain sums
     std::vector<int2> desc;
     std::vector<int> nstart(pp.nnodes + 1);
     for (int i = 0; i < pp.nnodes; ++i) {
