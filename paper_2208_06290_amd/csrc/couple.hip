@@ -16,7 +16,7 @@
 //   (eq. "e:node3") or the transposed solve used by the adjoint.
 // Lanes own rows of the right-hand side (2r <= 128 -> two rows per lane) and
 // the pivot value of each elimination step is broadcast with readlane.
-#include "internal.h"
+#include "wave.h"
 
 namespace hodlr {
 
@@ -195,17 +195,9 @@ __device__ __forceinline__ void block_lu(T* K, int n2, int lane, int w, int* spi
       for (int c = 0; c < 16; ++c) kj = (c == jc) ? kc[c] : kj;
       T v = done ? T(-1) : fabs(kj);
       if (!done && !(v == v)) v = T(INFINITY);
-      int key = done ? 0x7fffffff : mypos;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const T ov = __shfl_xor(v, off, 64);
-        const int ok = __shfl_xor(key, off, 64);
-        if (ov > v || (ov == v && ok < key)) {
-          v = ov;
-          key = ok;
-        }
-      }
-      const int bk = __builtin_amdgcn_readfirstlane(key);  // pivot position (uniform)
+      T vmax;
+      int bk;  // pivot position (uniform)
+      wave_argmax(v, done ? 0x7fffffff : mypos, vmax, bk);
       const unsigned long long sel = __ballot(!done && mypos == bk);
       const int plane = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(sel));
       const T pv = bcast(kj, plane);

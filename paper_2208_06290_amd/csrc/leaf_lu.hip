@@ -27,6 +27,7 @@
 //          lower), [1][kb] = inv(U_kb,kb) (upper); padded rows act as identity
 // First exactly-zero pivot -> atomicMin(info, leaf << 20 | column).
 #include "mfma.h"
+#include "wave.h"
 
 namespace hodlr {
 
@@ -167,16 +168,10 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
         const bool cand = own && !done;
         T v = cand ? fabs(r[j]) : T(-1);
         if (cand && !(v == v)) v = T(INFINITY);  // a NaN can still be chosen
-        int key = cand ? mypos : 0x7fffffff;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          const T ov = __shfl_xor(v, off, 64);
-          const int ok = __shfl_xor(key, off, 64);
-          if (ov > v || (ov == v && ok < key)) {
-            v = ov;
-            key = ok;
-          }
-        }
+        T vmax;
+        int key;
+        wave_argmax(v, cand ? mypos : 0x7fffffff, vmax, key);
+        v = vmax;
         if (cand && mypos == key) {
 #pragma unroll
           for (int cc = 0; cc < kCW; ++cc) crow_[sb][w][cc] = r[cc];
