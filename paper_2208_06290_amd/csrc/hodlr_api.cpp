@@ -158,7 +158,9 @@ struct hodlr_factors {
   int32_t* d_rpre = nullptr;
   std::vector<Tile*> d_tiles;                 // per tile level q = 0..L
   std::vector<int> ntiles;                    // per q
+  std::vector<std::vector<Tile>> h_tiles;     // per q (host copy)
   std::vector<int> tiles_aligned;             // per q: every tile height is a multiple of 16
+  int64_t ldy = 0, gsy = 256;                 // Y layout: row i, column c at (i >> 8) * gsy + (i & 255) + c * ldy
   std::vector<std::vector<int>> tile_start;   // per q, 2^q + 1
   std::map<std::pair<int, int>, ProdPlan> prods;
   // factors (T = compute element type)
@@ -303,11 +305,13 @@ hodlr_status plan(hodlr_factors* F) {
   F->d_tiles.assign(L + 1, nullptr);
   F->ntiles.assign(L + 1, 0);
   F->tiles_aligned.assign(L + 1, 0);
+  F->h_tiles.assign(L + 1, {});
   F->tile_start.assign(L + 1, {});
   std::vector<Tile> tl;
   for (int q = 0; q <= L; ++q) {
     build_tiles(F, q, tl, F->tile_start[q]);
     F->ntiles[q] = (int)tl.size();
+    F->h_tiles[q] = tl;
     F->tiles_aligned[q] = 1;
     for (const Tile& t : tl)
       if (t.nrows % 16) F->tiles_aligned[q] = 0;
@@ -351,7 +355,19 @@ hodlr_status allocate_factors(hodlr_factors* F) {
   F->udinv = b;
   if ((s = M.alloc(&b, nl * 2 * (mm / 16) * 256 * ts))) return s;
   F->invl = b;
-  if ((s = M.alloc(&b, (size_t)F->n * F->R * ts))) return s;
+  // Y in the row-group blocked layout (each 256-row group of all R columns
+  // contiguous) when no leaf and no tile crosses a 256-row boundary, else
+  // column-major with leading dimension N
+  bool blocked = F->R > 0;
+  for (int a = 0; a < F->nleaf && blocked; ++a)
+    if ((F->off[a] >> 8) != ((F->off[a + 1] - 1) >> 8)) blocked = false;
+  for (int q = 0; q <= L && blocked; ++q)
+    for (const Tile& t : F->h_tiles[q])
+      if ((t.row0 >> 8) != ((t.row0 + t.nrows - 1) >> 8)) blocked = false;
+  const int64_t ngroups = (F->n + 255) / 256;
+  F->ldy = blocked ? 256 : F->n;
+  F->gsy = blocked ? 256 * (int64_t)F->R : 256;
+  if ((s = M.alloc(&b, (size_t)(blocked ? ngroups * 256 : F->n) * F->R * ts))) return s;
   F->Y = b;
   F->koff.assign(L + 1, 0);
   F->kvoff.assign(L + 1, 0);
@@ -432,12 +448,13 @@ hodlr_status run_factor(hodlr_factors* F, hipStream_t st) {
                                       tp<T>(F->udinv), tp<T>(F->invl), F->d_info)));
   if (F->R > 0)
     HL("leaf_trsm", (launch_leaf_trsm<T, S>(st, 0, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->perm,
-                                            tp<T>(F->invl), U, F->ldu, Y, N, F->R)));
+                                            tp<T>(F->invl), U, F->ldu, Y, F->ldy, F->R, 256, F->gsy)));
   if (L > 0) {
     // products V^T Y for the children of level L-1 (the leaves)
-    HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], F->tiles_aligned[L], Y, N, F->R, (const T*)nullptr, N, 0,
-                                                 (const T*)nullptr, 0, 0, 0, V + (int64_t)F->Rp[L - 1] * F->ldv,
-                                                 F->ldv, F->ranks[L - 1], tp<T>(F->P))));
+    HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], F->tiles_aligned[L], Y, F->ldy, F->R,
+                                                 (const T*)nullptr, F->ldy, 0, (const T*)nullptr, 0, 0, 0,
+                                                 V + (int64_t)F->Rp[L - 1] * F->ldv, F->ldv, F->ranks[L - 1],
+                                                 tp<T>(F->P), GroupStrides{F->gsy, F->gsy, 256})));
     for (int p = L - 1; p >= 0; --p) {
       const int q = p + 1;
       const int r = F->ranks[q - 1];
@@ -458,15 +475,16 @@ hodlr_status run_factor(hodlr_factors* F, hipStream_t st) {
                                                 tp<T>(F->Kinv) + F->kioff[p], tp<T>(F->W), 2 * r, Rp)));
       if (p > 0 && r > 0) {
         HL("level_pass",
-           (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], F->tiles_aligned[q], Y, N, Rp, Y + (int64_t)Rp * N, N, r,
-                                       tp<T>(F->W), 2 * r, (int64_t)2 * r * Rp, 0,
-                                       V + (int64_t)F->Rp[p - 1] * F->ldv, F->ldv, F->ranks[p - 1], tp<T>(F->P))));
+           (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], F->tiles_aligned[q], Y, F->ldy, Rp,
+                                       Y + (int64_t)Rp * F->ldy, F->ldy, r, tp<T>(F->W), 2 * r, (int64_t)2 * r * Rp, 0,
+                                       V + (int64_t)F->Rp[p - 1] * F->ldv, F->ldv, F->ranks[p - 1], tp<T>(F->P),
+                                       GroupStrides{F->gsy, F->gsy, 256})));
       } else if (p > 0) {
         // rank-0 children: no update; products for level p still needed
-        HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], F->tiles_aligned[q], Y, N, Rp, (const T*)nullptr, N,
-                                                     0, (const T*)nullptr, 0, 0, 0,
+        HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], F->tiles_aligned[q], Y, F->ldy,
+                                                     Rp, (const T*)nullptr, F->ldy, 0, (const T*)nullptr, 0, 0, 0,
                                                      V + (int64_t)F->Rp[p - 1] * F->ldv, F->ldv, F->ranks[p - 1],
-                                                     tp<T>(F->P))));
+                                                     tp<T>(F->P), GroupStrides{F->gsy, F->gsy, 256})));
       }
     }
   }
@@ -578,16 +596,18 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
       const int kb = p > 0 ? F->ranks[p - 1] : 0;
       if (r == 0 && kb == 0) continue;
       HL("solve_pass", (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], F->tiles_aligned[q], X, ldx, nrhs,
-                                                   Y + (int64_t)F->Rp[p] * N, N, r, w, 2 * r, (int64_t)2 * r * nrhs, 0,
+                                                   Y + (int64_t)F->Rp[p] * F->ldy, F->ldy, r, w, 2 * r,
+                                                   (int64_t)2 * r * nrhs, 0,
                                                    p > 0 ? V + (int64_t)F->Rp[p - 1] * F->ldv : nullptr, F->ldv, kb,
-                                                   P)));
+                                                   P, GroupStrides{256, F->gsy, 256})));
     }
     return HODLR_OK;
   }
   // adjoint: top level first, transposed coupling solves, leaves last
   if (L > 0) {
     HL("adjoint_pass", (launch_level_pass<T, S, T>(st, F->ntiles[1], F->d_tiles[1], F->tiles_aligned[1], X, ldx, nrhs, (const S*)nullptr,
-                                                   N, 0, (const T*)nullptr, 0, 0, 0, Y, N, F->ranks[0], P)));
+                                                   N, 0, (const T*)nullptr, 0, 0, 0, Y, F->ldy, F->ranks[0], P,
+                                                   GroupStrides{256, 256, F->gsy})));
     for (int p = 0; p < L; ++p) {
       const int q = p + 1;
       const int r = F->ranks[q - 1];
@@ -607,7 +627,8 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
       HL("adjoint_pass", (launch_level_pass<T, S, T>(st, F->ntiles[tq], F->d_tiles[tq], F->tiles_aligned[tq], X, ldx, nrhs,
                                                      V + (int64_t)F->Rp[p] * F->ldv, F->ldv, r, w, 2 * r,
                                                      (int64_t)2 * r * nrhs, tq - q,
-                                                     q < L ? Y + (int64_t)F->Rp[q] * N : nullptr, N, kb, P)));
+                                                     q < L ? Y + (int64_t)F->Rp[q] * F->ldy : nullptr, F->ldy, kb, P,
+                                                     GroupStrides{256, 256, F->gsy})));
     }
   }
   HL("leaf_solve_t", (launch_leaf_trsm<T, T>(st, 1, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->perm,
@@ -916,9 +937,11 @@ hodlr_status hodlr_factors_y(const hodlr_factors* F, double* Yo, int64_t ldy, vo
   if (F->R == 0) return HODLR_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (F->compute == HODLR_F64)
-    HL("convert", (launch_convert<double, double>(st, F->n, F->R, static_cast<const double*>(F->Y), F->n, Yo, ldy)));
+    HL("convert", (launch_convert<double, double>(st, F->n, F->R, static_cast<const double*>(F->Y), F->ldy, Yo, ldy,
+                                                  F->gsy)));
   else
-    HL("convert", (launch_convert<double, float>(st, F->n, F->R, static_cast<const float*>(F->Y), F->n, Yo, ldy)));
+    HL("convert", (launch_convert<double, float>(st, F->n, F->R, static_cast<const float*>(F->Y), F->ldy, Yo, ldy,
+                                                 F->gsy)));
   return HODLR_OK;
 }
 

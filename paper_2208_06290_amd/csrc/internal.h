@@ -72,7 +72,7 @@ hipError_t launch_leaf_lu(hipStream_t s, int nleaf, int ldl, const int64_t* d_le
 template <typename T, typename S>
 hipError_t launch_leaf_trsm(hipStream_t s, int trans, int nleaf, int ldl, const int64_t* d_leaf_off, const T* lu,
                             const int32_t* perm, const T* dinv, const S* B, int64_t ldb, T* X, int64_t ldx,
-                            int ncols);
+                            int ncols, int64_t gsb = 256, int64_t gsx = 256);
 
 // The same solves for nblk equal blocks of m rows (m <= ldl): block g's rows start at X + g * ostride.
 template <typename T>
@@ -85,10 +85,21 @@ hipError_t launch_block_trsm(hipStream_t s, int trans, int nblk, int ldl, int m,
 // nd = tile.node >> node_shift; W for node nd starts at W + (nd >> 1) * w_pstride + (nd & 1) * ka, ld = w_ld.
 // P_tile starts at P + tile * kb * nz, col-major ld = kb.
 // tiles_aligned: every tile height is a multiple of 16 (enables the fast kernel).
+// Row addressing of the Z, A1 and B1 operands: row i of an operand lives at
+// (i >> 8) * gs + (i & 255) (plus column * ld).  gs = 256 is the plain
+// column-major layout; gs = 256 * ncols with ld = 256 is the row-group blocked
+// layout (each 256-row group of all columns contiguous), valid when no tile
+// crosses a 256-row boundary.
+struct GroupStrides {
+  int64_t z = 256, a = 256, b = 256;
+};
+__host__ __device__ __forceinline__ int64_t group_row(int64_t row, int64_t gs) { return (row >> 8) * gs + (row & 255); }
+
 template <typename TZ, typename SA, typename SB>
 hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int tiles_aligned, TZ* Z, int64_t ldz, int nz,
                              const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld,
-                             int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P);
+                             int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
+                             GroupStrides gs = GroupStrides());
 
 // Segment sums of tile partials: out[s] = sum of tiles [desc[s].x, desc[s].x + desc[s].y).
 template <typename T>
@@ -140,6 +151,7 @@ hipError_t launch_axpy_up(hipStream_t s, int64_t n, int nrhs, const T* d, int64_
                           int64_t ldx);
 hipError_t launch_residual(hipStream_t s, int64_t n, int nrhs, const double* B, int64_t ldb, double* AX, int64_t ldax);
 template <typename T, typename S>
-hipError_t launch_convert(hipStream_t s, int64_t rows, int cols, const S* in, int64_t ldi, T* out, int64_t ldo);
+hipError_t launch_convert(hipStream_t s, int64_t rows, int cols, const S* in, int64_t ldi, T* out, int64_t ldo,
+                          int64_t gsi = 256);
 
 }  // namespace hodlr

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
                                                              int64_t ostride, int mfix, const T* __restrict__ lu,
                                                              const int32_t* __restrict__ perm,
                                                              const T* __restrict__ dinv, const S* B, int64_t ldb,
-                                                             T* X, int64_t ldx, int ncols, int nchunks) {
+                                                             T* X, int64_t ldx, int ncols, int nchunks, int64_t gsb,
+                                                             int64_t gsx) {
   using M = Mfma<T>;
   using V = typename M::V;
   __shared__ T invA[16 * 256];     // inverse diagonal blocks of the current sweep, [kb][i][j]
@@ -49,6 +50,10 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
     o = (int64_t)a * ostride;
     m = mfix;
   }
+  // first row of the block in B and X (row i of an operand at (i >> 8) gs + (i & 255); a block
+  // never crosses a 256-row boundary of an operand in the row-group blocked layout)
+  const S* Bb = B + group_row(o, gsb);
+  T* Xb = X + group_row(o, gsx);
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lq = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c0 = chunk * 64;
@@ -85,7 +90,7 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int col = c0 + 16 * cb + M::crow(lq, t);
-        const T v = (T)B[o + src + (int64_t)min(col, ncols - 1) * ldb];
+        const T v = (T)Bb[src + (int64_t)min(col, ncols - 1) * ldb];
         acc[q][cb][t] = (row < m && col < ncols) ? v : T(0);
       }
   }
@@ -168,7 +173,7 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int col = c0 + 16 * cb + M::crow(lq, t);
-          if (col < ncols) X[o + dst + (int64_t)col * ldx] = acc[q][cb][t];
+          if (col < ncols) Xb[dst + (int64_t)col * ldx] = acc[q][cb][t];
         }
     }
   }
@@ -177,7 +182,7 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
 template <typename T, typename S>
 static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const int64_t* d_off, int64_t ostride,
                               int mfix, const T* lu, const int32_t* perm, const T* dinv, const S* B, int64_t ldb, T* X,
-                              int64_t ldx, int ncols) {
+                              int64_t ldx, int ncols, int64_t gsb, int64_t gsx) {
   if (nblk == 0 || ncols == 0) return hipSuccess;
   if (ldl % 16 || ldl > 256) return hipErrorInvalidValue;
   const int nchunks = (ncols + 63) / 64;
@@ -185,7 +190,7 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
 #define HODLR_TS(TR, NC)                                                                                  \
   hipLaunchKernelGGL((trsm_kernel<T, S, TR, NC>), dim3((unsigned)grid), dim3(kTsThreads), 0, s, ldl, d_off, ostride, \
-                     mfix, lu, perm, dinv, B, ldb, X, ldx, ncols, nchunks)
+                     mfix, lu, perm, dinv, B, ldb, X, ldx, ncols, nchunks, gsb, gsx)
   // one 16-column block per chunk for narrow right-hand sides, four otherwise
   if (trans) {
     if (ncols <= 16) HODLR_TS(1, 1); else HODLR_TS(1, 4);
@@ -199,25 +204,25 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
 template <typename T, typename S>
 hipError_t launch_leaf_trsm(hipStream_t s, int trans, int nleaf, int ldl, const int64_t* d_leaf_off, const T* lu,
                             const int32_t* perm, const T* dinv, const S* B, int64_t ldb, T* X, int64_t ldx,
-                            int ncols) {
-  return launch_trsm<T, S>(s, trans, nleaf, ldl, d_leaf_off, 0, 0, lu, perm, dinv, B, ldb, X, ldx, ncols);
+                            int ncols, int64_t gsb, int64_t gsx) {
+  return launch_trsm<T, S>(s, trans, nleaf, ldl, d_leaf_off, 0, 0, lu, perm, dinv, B, ldb, X, ldx, ncols, gsb, gsx);
 }
 
 template <typename T>
 hipError_t launch_block_trsm(hipStream_t s, int trans, int nblk, int ldl, int m, int64_t ostride, const T* lu,
                              const int32_t* perm, const T* dinv, T* X, int64_t ldx, int ncols) {
-  return launch_trsm<T, T>(s, trans, nblk, ldl, nullptr, ostride, m, lu, perm, dinv, X, ldx, X, ldx, ncols);
+  return launch_trsm<T, T>(s, trans, nblk, ldl, nullptr, ostride, m, lu, perm, dinv, X, ldx, X, ldx, ncols, 256, 256);
 }
 
 template hipError_t launch_leaf_trsm<double, double>(hipStream_t, int, int, int, const int64_t*, const double*,
                                                      const int32_t*, const double*, const double*, int64_t,
-                                                     double*, int64_t, int);
+                                                     double*, int64_t, int, int64_t, int64_t);
 template hipError_t launch_leaf_trsm<float, double>(hipStream_t, int, int, int, const int64_t*, const float*,
                                                     const int32_t*, const float*, const double*, int64_t,
-                                                    float*, int64_t, int);
+                                                    float*, int64_t, int, int64_t, int64_t);
 template hipError_t launch_leaf_trsm<float, float>(hipStream_t, int, int, int, const int64_t*, const float*,
                                                    const int32_t*, const float*, const float*, int64_t, float*,
-                                                   int64_t, int);
+                                                   int64_t, int, int64_t, int64_t);
 template hipError_t launch_block_trsm<double>(hipStream_t, int, int, int, int, int64_t, const double*,
                                               const int32_t*, const double*, double*, int64_t, int);
 template hipError_t launch_block_trsm<float>(hipStream_t, int, int, int, int, int64_t, const float*, const int32_t*,

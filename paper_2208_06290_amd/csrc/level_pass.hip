@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
                                                                    const TZ* __restrict__ W, int64_t w_ld,
                                                                    int64_t w_pstride, int node_shift,
                                                                    const SB* __restrict__ B1, int64_t ldb,
-                                                                   int kb_total, TZ* __restrict__ P) {
+                                                                   int kb_total, TZ* __restrict__ P, GroupStrides gs) {
   using M = Mfma<TZ>;
   using V = typename M::V;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -45,8 +45,11 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
   const int zchunk = (lid / bchunks) % zchunks;
   const int tile = lid / (bchunks * zchunks);
   const Tile tl = tiles[tile];
-  const int64_t row0 = tl.row0;
   const int nrows = tl.nrows;
+  // first row of the tile in each operand (rows inside a tile are contiguous)
+  TZ* Zt = Z + group_row(tl.row0, gs.z);
+  const SA* At = A1 ? A1 + group_row(tl.row0, gs.a) : A1;
+  const SB* Bt = B1 ? B1 + group_row(tl.row0, gs.b) : B1;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lq = lane >> 4;
   const int c0 = zchunk * 64;
   const int ncb = min(4, (nz - c0 + 15) >> 4);
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
         const int row = wr0 + 16 * rb + M::crow(lq, t);
         const int col = c0 + 16 * cb + li;
         const bool ok = row < nrows && col < nz;
-        const TZ v = Z[row0 + min(row, nrows - 1) + (int64_t)min(col, nz - 1) * ldz];
+        const TZ v = Zt[min(row, nrows - 1) + (int64_t)min(col, nz - 1) * ldz];
         dst[cb][t] = ok ? v : TZ(0);
       }
   };
@@ -97,7 +100,7 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
       const int rowc = min(row, nrows - 1);
       for (int ks = 0; ks < nks; ++ks) {
         const int kk = 4 * ks + lq;
-        const TZ av = -(TZ)A1[row0 + rowc + (int64_t)min(kk, ka - 1) * lda];
+        const TZ av = -(TZ)At[rowc + (int64_t)min(kk, ka - 1) * lda];
         const TZ a = (row < nrows && kk < ka) ? av : TZ(0);
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
         for (int t = 0; t < 4; ++t) {
           const int rr = wr0 + 16 * rb + M::crow(lq, t);
           const int col = c0 + 16 * cb + li;
-          if (cb < ncb && rr < nrows && col < nz) Z[row0 + rr + (int64_t)col * ldz] = acc[cb][t];
+          if (cb < ncb && rr < nrows && col < nz) Zt[rr + (int64_t)col * ldz] = acc[cb][t];
         }
     }
     if (kb > 0) {
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
           const int kr = 16 * mb + li;
-          const TZ bv = (TZ)B1[row0 + min(rr, nrows - 1) + (int64_t)(kc0 + min(kr, kb - 1)) * ldb];
+          const TZ bv = (TZ)Bt[min(rr, nrows - 1) + (int64_t)(kc0 + min(kr, kb - 1)) * ldb];
           bo[mb] = (rr < nrows && kr < kb) ? bv : TZ(0);
         }
 #pragma unroll
@@ -179,7 +182,7 @@ template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int M
 __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level_pass_fast_kernel(
     const Tile* __restrict__ tiles, int zchunks, int zc_base, int bchunks, TZ* Z, int64_t ldz, int nz, const SA* __restrict__ A1,
     int64_t lda, const TZ* __restrict__ W, int64_t w_ld, int64_t w_pstride, int node_shift,
-    const SB* __restrict__ B1, int64_t ldb, int kb_total, TZ* __restrict__ P) {
+    const SB* __restrict__ B1, int64_t ldb, int kb_total, TZ* __restrict__ P, GroupStrides gs) {
   using M = Mfma<TZ>;
   using V = typename M::V;
   constexpr int ka = 4 * NKS;
@@ -197,7 +200,6 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
   const int zchunk = (lid / bchunks) % zchunks;
   const int tile = lid / (bchunks * zchunks);
   const Tile tl = tiles[tile];
-  const int64_t row0 = tl.row0;
   const int nrows = tl.nrows;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lq = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: addresses stay scalar
@@ -218,9 +220,10 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
     }
   }
 
-  const auto zr = buf_rsrc(Z + row0 + wr0 + (int64_t)c0 * ldz);
-  const auto ar = buf_rsrc(NKS > 0 ? A1 + row0 + wr0 : A1);  // A1 / B1 are null when unused
-  const auto br = buf_rsrc(prod ? B1 + row0 + wr0 + (int64_t)kc0 * ldb : B1);
+  // first row of this wave in each operand (rows inside a tile are contiguous)
+  const auto zr = buf_rsrc(Z + group_row(tl.row0, gs.z) + wr0 + (int64_t)c0 * ldz);
+  const auto ar = buf_rsrc(NKS > 0 ? A1 + group_row(tl.row0, gs.a) + wr0 : A1);  // A1 / B1 are null when unused
+  const auto br = buf_rsrc(prod ? B1 + group_row(tl.row0, gs.b) + wr0 + (int64_t)kc0 * ldb : B1);
   const uint32_t zrow = (uint32_t)li * (uint32_t)sizeof(TZ);
   const uint32_t zl = zrow + (uint32_t)((int64_t)M::crow_l(lq) * ldz) * (uint32_t)sizeof(TZ);
   const uint32_t al = (uint32_t)(li + (int64_t)lq * lda) * (uint32_t)sizeof(SA);
@@ -362,7 +365,7 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
 template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB>
 static hipError_t launch_fast(hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z, int64_t ldz,
                               const SA* A1, int64_t lda, const TZ* W, int64_t w_ld, int64_t w_pstride,
-                              int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P) {
+                              int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P, GroupStrides gs) {
   constexpr int kCw = 16 * NCB;
   const size_t smem_main = sizeof(TZ) * (kCw * 4 * (size_t)NKS + 4 * (16 * kZtLd + 16 * (16 * MB + 1)));
   const size_t smem_red = MB > 0 ? sizeof(TZ) * 2 * 16 * MB * kCw : 0;
@@ -380,7 +383,7 @@ static hipError_t launch_fast(hipStream_t s, int ntiles, int nz, int bchunks, co
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kLpThreads), smem, s, tiles, zchunks, part == 0 ? 0 : nfull,
-                       bchunks, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);
+                       bchunks, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P, gs);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -390,10 +393,11 @@ static hipError_t launch_fast(hipStream_t s, int ntiles, int nz, int bchunks, co
 template <typename TZ, typename SA, typename SB, int MB, int NCB>
 static hipError_t launch_fast_nks(int nks, hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z,
                                   int64_t ldz, const SA* A1, int64_t lda, const TZ* W, int64_t w_ld,
-                                  int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P) {
+                                  int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
+                                  GroupStrides gs) {
 #define HODLR_LPF(NKSV)                                                                                       \
   return launch_fast<TZ, SA, SB, MB, NKSV, NCB>(s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld, w_pstride, \
-                                                 node_shift, B1, ldb, kb, P)
+                                                 node_shift, B1, ldb, kb, P, gs)
   switch (nks) {
     case 0: HODLR_LPF(0);
     case 4: HODLR_LPF(4);
@@ -407,12 +411,12 @@ static hipError_t launch_fast_nks(int nks, hipStream_t s, int ntiles, int nz, in
 template <typename TZ, typename SA, typename SB, int NCB>
 static hipError_t launch_fast_all(hipStream_t s, int ntiles, const Tile* tiles, TZ* Z, int64_t ldz, int nz,
                                   const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld, int64_t w_pstride,
-                                  int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P) {
+                                  int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P, GroupStrides gs) {
   const int bchunks = kb > 0 ? (kb + 63) / 64 : 1;
   const int nks = ka / 4;
 #define HODLR_LPM(MBV)                                                                                            \
   return launch_fast_nks<TZ, SA, SB, MBV, NCB>(nks, s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,      \
-                                                w_pstride, node_shift, B1, ldb, kb, P)
+                                                w_pstride, node_shift, B1, ldb, kb, P, gs)
   switch (kb > 0 ? std::min(kb, 64) / 16 : 0) {
     case 0: HODLR_LPM(0);
     case 1: HODLR_LPM(1);
@@ -426,7 +430,8 @@ static hipError_t launch_fast_all(hipStream_t s, int ntiles, const Tile* tiles, 
 template <typename TZ, typename SA, typename SB>
 hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int tiles_aligned, TZ* Z, int64_t ldz,
                              int nz, const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld,
-                             int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P) {
+                             int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
+                             GroupStrides gs) {
   if (ntiles == 0 || nz == 0 || (ka == 0 && kb == 0)) return hipSuccess;
   const int zchunks = (nz + 63) / 64;
   const int bchunks = kb > 0 ? (kb + 63) / 64 : 1;
@@ -440,9 +445,9 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int t
   if (tiles_aligned && small_ld && ka % 16 == 0 && kb % 16 == 0) {
     if (nz <= 16)
       return launch_fast_all<TZ, SA, SB, 1>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride, node_shift,
-                                            B1, ldb, kb, P);
+                                            B1, ldb, kb, P, gs);
     return launch_fast_all<TZ, SA, SB, 4>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride, node_shift,
-                                          B1, ldb, kb, P);
+                                          B1, ldb, kb, P, gs);
   }
   const int mbn = kb > 0 ? (min(kb, 64) + 15) / 16 : 1;
   const size_t smem_red = kb > 0 ? sizeof(TZ) * 4 * 16 * mbn * 64 : 0;
@@ -454,7 +459,7 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int t
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem); \
     if (e != hipSuccess) return e;                                                                           \
     hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kLpThreads), smem, s, tiles, zchunks, bchunks, Z, ldz, nz, \
-                       A1, lda, ka, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P);                                    \
+                       A1, lda, ka, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P, gs);                                \
   }
   switch (mbn) {
     case 1: HODLR_LP(1) break;
@@ -469,7 +474,7 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int t
 #define HODLR_LP_INST(TZ, SA, SB)                                                                             \
   template hipError_t launch_level_pass<TZ, SA, SB>(hipStream_t, int, const Tile*, int, TZ*, int64_t, int, const SA*, \
                                                     int64_t, int, const TZ*, int64_t, int64_t, int,           \
-                                                    const SB*, int64_t, int, TZ*);
+                                                    const SB*, int64_t, int, TZ*, GroupStrides);
 HODLR_LP_INST(double, double, double)
 HODLR_LP_INST(float, float, double)
 HODLR_LP_INST(float, double, float)

@@ -383,21 +383,23 @@ hipError_t launch_residual(hipStream_t s, int64_t n, int nrhs, const double* B, 
 }
 
 template <typename T, typename S>
-__global__ void convert_kernel(int64_t rows, const S* __restrict__ in, int64_t ldi, T* __restrict__ out, int64_t ldo) {
+__global__ void convert_kernel(int64_t rows, const S* __restrict__ in, int64_t ldi, int64_t gsi, T* __restrict__ out,
+                               int64_t ldo) {
   const int j = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= rows) return;
-  out[i + (int64_t)j * ldo] = (T)in[i + (int64_t)j * ldi];
+  out[i + (int64_t)j * ldo] = (T)in[group_row(i, gsi) + (int64_t)j * ldi];
 }
 template <typename T, typename S>
-hipError_t launch_convert(hipStream_t s, int64_t rows, int cols, const S* in, int64_t ldi, T* out, int64_t ldo) {
+hipError_t launch_convert(hipStream_t s, int64_t rows, int cols, const S* in, int64_t ldi, T* out, int64_t ldo,
+                          int64_t gsi) {
   if (rows == 0 || cols == 0) return hipSuccess;
   hipLaunchKernelGGL((convert_kernel<T, S>), dim3((unsigned)((rows + 255) / 256), cols), dim3(256), 0, s, rows, in, ldi,
-                     out, ldo);
+                     gsi, out, ldo);
   return hipGetLastError();
 }
-template hipError_t launch_convert<double, double>(hipStream_t, int64_t, int, const double*, int64_t, double*, int64_t);
-template hipError_t launch_convert<double, float>(hipStream_t, int64_t, int, const float*, int64_t, double*, int64_t);
-template hipError_t launch_convert<float, double>(hipStream_t, int64_t, int, const double*, int64_t, float*, int64_t);
+template hipError_t launch_convert<double, double>(hipStream_t, int64_t, int, const double*, int64_t, double*, int64_t, int64_t);
+template hipError_t launch_convert<double, float>(hipStream_t, int64_t, int, const float*, int64_t, double*, int64_t, int64_t);
+template hipError_t launch_convert<float, double>(hipStream_t, int64_t, int, const double*, int64_t, float*, int64_t, int64_t);
 
 }  // namespace hodlr
