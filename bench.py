@@ -31,6 +31,15 @@ sys.path.insert(0, ROOT)
 
 PEAK = dict(hbm=8.0e12, f64=78.6e12, f32=157.3e12, bf16=2.5e15)
 
+# HBM traffic of the level pass per launch (one tree level) of the FP64
+# factorization at N = 2^20, leaf 256, rank 32, from two rocprofv3 counter runs
+# (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, the factors that a plain 1 GiB copy
+# reads back; summary and commands in profiles/level_pass_traffic_n1m_fp64.md).
+# It is reported only while the kernel source is the one it was measured on.
+LEVEL_PASS_TRAFFIC = dict(
+    source_sha256="02658ca76f654d868ce2600379a00d3340be48ece16050a8d90b4e1155b88651",
+    n=1 << 20, leaf=256, rank=32, bytes_per_launch=4.26e9)
+
 
 def _say(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -196,7 +205,7 @@ def main():
         if name in per_kernel and "bound" in per_kernel[name]:
             pk = per_kernel[name]
             roof = dict(kernel=name, bound=pk["bound"], achieved=pk["achieved"], peak=pk["peak"], unit=pk["unit"],
-                        frac=pk["frac"], traffic=None)
+                        frac=pk["frac"], traffic=measured_traffic(name, inp))
             break
 
     cpu = None
@@ -226,6 +235,23 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
+
+
+def measured_traffic(kernel, inp):
+    """Counter-measured HBM bytes per launch of `kernel`, or None when no
+    measurement matches this workload and the current kernel source."""
+    import hashlib
+
+    t = LEVEL_PASS_TRAFFIC
+    if kernel != "level_pass" or inp.n != t["n"] or int(inp.m_max) != t["leaf"]:
+        return None
+    if any(int(r) != t["rank"] for r in inp.ranks):
+        return None
+    src = os.path.join(ROOT, "paper_2208_06290_amd", "csrc", "level_pass.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
+            return None
+    return t["bytes_per_launch"]
 
 
 def cpu_baseline(inp, b, rows=65536):
