@@ -172,6 +172,7 @@ def main():
     if not args.no_mixed:
         mixed, kt32, F32 = run_path("fp32", True)
         del F32
+        mixed["kernels_ms_per_step"] = {k: ms / args.steps for k, (ms, cnt) in sorted(kt32.items(), key=lambda kv: -kv[1][0])}
         _say(f"fp32+IR: {mixed}")
 
     # roofline of the dominant FP64 kernel (per-launch averages from HIP events)

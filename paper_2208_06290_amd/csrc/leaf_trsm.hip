@@ -96,47 +96,59 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
   }
   __syncthreads();  // invA staged; B may alias X: all loads of the chunk precede any store
 
-  int step = 0;
+  // X_k^T = B_k^T inv(M_kk)^T for the wave owning block k (accumulator block
+  // q): the block turns around through LDS to become the A operand; the
+  // result stays in the accumulators and is published as X_k[row][col]
+  auto owner = [&](int q, int k, T* xb) {
 #pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) twv[li * kTwLd + M::crow(lq, t)] = acc[q][cb][t];
+      V nv = vzero<V>();
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        nv = M::mma(twv[(4 * ks + lq) * kTwLd + li], invA[k * 256 + li * 16 + 4 * ks + lq], nv);
+      acc[q][cb] = nv;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) xb[li * 64 + 16 * cb + M::crow(lq, t)] = nv[t];
+    }
+  };
+  // B_b^T -= X_k^T M_bk^T on accumulator block q2
+  auto update = [&](int q2, const T (&av)[4][4], const T* xb) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        acc[q2][cb] = M::mma(xb[(4 * ks + lq) * 64 + 16 * cb + li], av[q2][ks], acc[q2][cb]);
+  };
+
+  // The steps are unrolled so that every block index is a compile-time
+  // constant; steps past the last block of a short leaf are skipped (uniform).
+#pragma clang loop unroll(full)
   for (int sweep = 0; sweep < 2; ++sweep) {
     if (sweep == 1) {
       __syncthreads();
       stage_inv(1);
       __syncthreads();
     }
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-      const int q = sweep == 0 ? qq : 3 - qq;
-      for (int ww = 0; ww < 4; ++ww) {
-        const int wk = sweep == 0 ? ww : 3 - ww;
-        const int k = 4 * q + wk;
-        if (k >= nbk) continue;  // uniform
-        T* xb = xk[step & 1];
-        ++step;
-        if (w == wk) {
-          // X_k^T = B_k^T inv(M_kk)^T: the block turns around through LDS to
-          // become the A operand; the result stays in the accumulators and is
-          // published as X_k[row][col]
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) twv[li * kTwLd + M::crow(lq, t)] = acc[q][cb][t];
-            V nv = vzero<V>();
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks)
-              nv = M::mma(twv[(4 * ks + lq) * kTwLd + li], invA[k * 256 + li * 16 + 4 * ks + lq], nv);
-            acc[q][cb] = nv;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) xb[li * 64 + 16 * cb + M::crow(lq, t)] = nv[t];
-          }
-        }
-        // B_b^T -= X_k^T M_bk^T for this wave's blocks on the far side of k; the
-        // factor operands M(16 b + li, 16 k + 4 ks + lq) do not depend on X_k
-        // and are fetched before the barrier (clamped in range, no branches)
+#pragma clang loop unroll(full)
+    for (int st = 0; st < 16; ++st) {
+      const int k = sweep == 0 ? st : 15 - st;
+      if (k < nbk) {  // uniform
+        const int q = k >> 2, wk = k & 3;
+        // step index within the sweep decides the X buffer (sweep 1 starts at nbk - 1)
+        const int sidx = sweep == 0 ? k : nbk - 1 - k;
+        T* xb = xk[sidx & 1];
+        T* xn = xk[(sidx + 1) & 1];
+        // the first step's X_k is formed here, later ones one step ahead (look-ahead)
+        if (sidx == 0 && w == wk) owner(q, k, xb);
+        // the factor operands M(16 b + li, 16 k + 4 ks + lq) of this wave's blocks
+        // on the far side of k do not depend on X_k: fetched before the barrier
+        // (clamped in range, no branches)
         T av[4][4];
 #pragma unroll
         for (int q2 = 0; q2 < 4; ++q2) {
-          if (sweep == 0 ? q2 < q : q2 > q) continue;  // never on the far side: resolved at compile time
+          if (sweep == 0 ? q2 < q : q2 > q) continue;  // never on the far side: compile time
           const int b = min(4 * q2 + w, nbk - 1);
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
@@ -145,18 +157,23 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
           }
         }
         __syncthreads();
+        // look-ahead: the wave owning the next block updates it first and forms
+        // X_next at once, so the next step starts without waiting for it
+        const int kn = sweep == 0 ? k + 1 : k - 1;
+        const bool nxt = sweep == 0 ? kn < nbk : kn >= 0;
+        const int qn = kn >> 2, wn = kn & 3;
+        const bool la = nxt && w == wn;  // uniform
+        if (la) {
+          update(qn, av, xb);
+          owner(qn, kn, xn);
+        }
 #pragma unroll
         for (int q2 = 0; q2 < 4; ++q2) {
           if (sweep == 0 ? q2 < q : q2 > q) continue;
           const int b = 4 * q2 + w;
-          const bool act = (sweep == 0 ? (q2 > q || w > wk) : (q2 < q || w < wk)) && b < nbk;  // uniform
-          if (act) {
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-              for (int cb = 0; cb < NCB; ++cb)
-                acc[q2][cb] = M::mma(xb[(4 * ks + lq) * 64 + 16 * cb + li], av[q2][ks], acc[q2][cb]);
-          }
+          const bool act = (sweep == 0 ? (q2 > q || w > wk) : (q2 < q || w < wk)) && b < nbk &&
+                           !(la && q2 == qn);  // uniform
+          if (act) update(q2, av, xb);
         }
       }
     }

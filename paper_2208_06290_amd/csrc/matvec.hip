@@ -37,7 +37,7 @@ hipError_t launch_tree_sum(hipStream_t s, int nnodes, int64_t elems, const doubl
 }
 
 // y(leaf rows, chunk) = op(D_a) x_a + U(I_a, :) G_a     (op = identity or transpose)
-template <typename S, int TRANS>
+template <typename S, int TRANS, int NCB>
 __global__ __launch_bounds__(kMvThreads) void matvec_apply_kernel(
     const int64_t* __restrict__ leaf_off, int L, const int32_t* __restrict__ rpre, int R, const S* __restrict__ D,
     int64_t ldd, const S* __restrict__ Ua, int64_t lda, const double* __restrict__ X, int64_t ldx,
@@ -48,69 +48,73 @@ __global__ __launch_bounds__(kMvThreads) void matvec_apply_kernel(
   const int m = (int)(leaf_off[leaf + 1] - o);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lq = lane >> 4;
   const int c0 = zc * 64;
-  const int ncb = min(4, (nrhs - c0 + 15) >> 4);
   const int wr0 = 64 * w;
-  d4 acc[4][4];
+  d4 acc[4][NCB];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = d4{0, 0, 0, 0};
+    for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = d4{0, 0, 0, 0};
+  // Operand loads are clamped into range and masked (no branches), and the
+  // K loops are unrolled so that several steps' loads are in flight at once.
   // leaf block
+#pragma unroll 4
   for (int k0 = 0; k0 < m; k0 += 4) {
-    const int kk = k0 + lq;
-    double av[4], bv[4];
+    const int kk = k0 + lq, kc = min(kk, m - 1);
+    double av[4], bv[NCB];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
-      const int row = wr0 + 16 * rb + li;
-      double v = 0.0;
-      if (row < m && kk < m) v = TRANS ? (double)D[o + kk + (int64_t)row * ldd] : (double)D[o + row + (int64_t)kk * ldd];
-      av[rb] = v;
+      const int row = wr0 + 16 * rb + li, rc = min(row, m - 1);
+      const double v = TRANS ? (double)D[o + kc + (int64_t)rc * ldd] : (double)D[o + rc + (int64_t)kc * ldd];
+      av[rb] = (row < m && kk < m) ? v : 0.0;
     }
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
+    for (int cb = 0; cb < NCB; ++cb) {
       const int col = c0 + 16 * cb + li;
-      bv[cb] = (kk < m && col < nrhs) ? X[o + kk + (int64_t)col * ldx] : 0.0;
+      const double v = X[o + kc + (int64_t)min(col, nrhs - 1) * ldx];
+      bv[cb] = (kk < m && col < nrhs) ? v : 0.0;
     }
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
-        if (cb < ncb) acc[rb][cb] = mma64(av[rb], bv[cb], acc[rb][cb]);
+      for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mma64(av[rb], bv[cb], acc[rb][cb]);
   }
   // low-rank blocks of every level
   for (int l = 1; l <= L; ++l) {
     const int cl0 = rpre[l - 1], cl1 = rpre[l];
+    if (cl1 == cl0) continue;
     const int node = leaf >> (L - l);
     const double* Sg = tree + tree_slot(l, node ^ 1) * R * nrhs;
+#pragma unroll 4
     for (int k0 = cl0; k0 < cl1; k0 += 4) {
-      const int kk = k0 + lq;
-      double av[4], bv[4];
+      const int kk = k0 + lq, kc = min(kk, cl1 - 1);
+      double av[4], bv[NCB];
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) {
         const int row = wr0 + 16 * rb + li;
-        av[rb] = (row < m && kk < cl1) ? (double)Ua[o + row + (int64_t)kk * lda] : 0.0;
+        const double v = (double)Ua[o + min(row, m - 1) + (int64_t)kc * lda];
+        av[rb] = (row < m && kk < cl1) ? v : 0.0;
       }
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
+      for (int cb = 0; cb < NCB; ++cb) {
         const int col = c0 + 16 * cb + li;
-        bv[cb] = (kk < cl1 && col < nrhs) ? Sg[kk + (int64_t)col * R] : 0.0;
+        const double v = Sg[kc + (int64_t)min(col, nrhs - 1) * R];
+        bv[cb] = (kk < cl1 && col < nrhs) ? v : 0.0;
       }
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-          if (cb < ncb) acc[rb][cb] = mma64(av[rb], bv[cb], acc[rb][cb]);
+        for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mma64(av[rb], bv[cb], acc[rb][cb]);
     }
   }
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int row = wr0 + 16 * rb + crow64(lq, t);
         const int col = c0 + 16 * cb + li;
-        if (cb < ncb && row < m && col < nrhs) Y[o + row + (int64_t)col * ldy] = acc[rb][cb][t];
+        if (row < m && col < nrhs) Y[o + row + (int64_t)col * ldy] = acc[rb][cb][t];
       }
 }
 
@@ -121,12 +125,15 @@ hipError_t launch_matvec_apply(hipStream_t s, int trans, int nleaf, int L, const
   if (nleaf == 0 || nrhs == 0) return hipSuccess;
   const int zchunks = (nrhs + 63) / 64;
   dim3 grid((unsigned)(nleaf * zchunks));
-  if (trans)
-    hipLaunchKernelGGL((matvec_apply_kernel<S, 1>), grid, dim3(kMvThreads), 0, s, d_leaf_off, L, d_rpre, R, D, ldd,
-                       Ua, lda, X, ldx, tree, Y, ldy, nrhs, zchunks);
-  else
-    hipLaunchKernelGGL((matvec_apply_kernel<S, 0>), grid, dim3(kMvThreads), 0, s, d_leaf_off, L, d_rpre, R, D, ldd,
-                       Ua, lda, X, ldx, tree, Y, ldy, nrhs, zchunks);
+#define HODLR_MV(TR, NC)                                                                                             \
+  hipLaunchKernelGGL((matvec_apply_kernel<S, TR, NC>), grid, dim3(kMvThreads), 0, s, d_leaf_off, L, d_rpre, R, D, ldd, \
+                     Ua, lda, X, ldx, tree, Y, ldy, nrhs, zchunks)
+  if (trans) {
+    if (nrhs <= 16) HODLR_MV(1, 1); else HODLR_MV(1, 4);
+  } else {
+    if (nrhs <= 16) HODLR_MV(0, 1); else HODLR_MV(0, 4);
+  }
+#undef HODLR_MV
   return hipGetLastError();
 }
 template hipError_t launch_matvec_apply<double>(hipStream_t, int, int, int, const int64_t*, const int32_t*, int,
