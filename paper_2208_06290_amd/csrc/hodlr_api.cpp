@@ -653,8 +653,16 @@ hodlr_status matvec_impl(hodlr_factors* F, hipStream_t st, int trans, int nrhs, 
       HL("mv_tree", launch_tree_sum(st, 1 << l, (int64_t)F->R * nrhs, tree + tree_slot(l + 1, 0) * F->R * nrhs,
                                     tree + tree_slot(l, 0) * F->R * nrhs));
   }
+  // every leaf exactly 256 rows (one row per lane of the 4 waves) and every level width a multiple of 4:
+  // the kernel needs no masks
+  bool full = true;
+  for (int a = 0; a < F->nleaf && full; ++a)
+    if (F->off[a + 1] - F->off[a] != 256) full = false;
+  for (int l = 0; l < L && full; ++l)
+    if (F->ranks[l] % 4) full = false;
   HL("mv_apply", (launch_matvec_apply<S>(st, trans, F->nleaf, L, F->d_off, F->d_rpre, F->R,
-                                         static_cast<const S*>(F->D), F->ldd, Ua, lda, X, ldx, tree, Yo, ldy, nrhs)));
+                                         static_cast<const S*>(F->D), F->ldd, Ua, lda, X, ldx, tree, Yo, ldy, nrhs,
+                                         full)));
   return HODLR_OK;
 }
 

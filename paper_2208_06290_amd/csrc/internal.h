@@ -130,7 +130,7 @@ __host__ __device__ inline int64_t tree_slot(int l, int node) { return ((int64_t
 template <typename S>
 hipError_t launch_matvec_apply(hipStream_t s, int trans, int nleaf, int L, const int64_t* d_leaf_off,
                                const int32_t* d_rpre, int R, const S* D, int64_t ldd, const S* Ua, int64_t lda,
-                               const double* X, int64_t ldx, const double* tree, double* Y, int64_t ldy, int nrhs);
+                               const double* X, int64_t ldx, const double* tree, double* Y, int64_t ldy, int nrhs, int full);
 
 // Gradient pieces.
 template <typename S>

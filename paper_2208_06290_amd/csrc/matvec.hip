@@ -37,7 +37,7 @@ hipError_t launch_tree_sum(hipStream_t s, int nnodes, int64_t elems, const doubl
 }
 
 // y(leaf rows, chunk) = op(D_a) x_a + U(I_a, :) G_a     (op = identity or transpose)
-template <typename S, int TRANS, int NCB>
+template <typename S, int TRANS, int NCB, bool FULL>
 __global__ __launch_bounds__(kMvThreads) void matvec_apply_kernel(
     const int64_t* __restrict__ leaf_off, int L, const int32_t* __restrict__ rpre, int R, const S* __restrict__ D,
     int64_t ldd, const S* __restrict__ Ua, int64_t lda, const double* __restrict__ X, int64_t ldx,
@@ -54,57 +54,55 @@ __global__ __launch_bounds__(kMvThreads) void matvec_apply_kernel(
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = d4{0, 0, 0, 0};
-  // Operand loads are clamped into range and masked (no branches), and the
-  // K loops are unrolled so that several steps' loads are in flight at once.
-  // leaf block
-#pragma unroll 4
-  for (int k0 = 0; k0 < m; k0 += 4) {
-    const int kk = k0 + lq, kc = min(kk, m - 1);
-    double av[4], bv[NCB];
+  // One K-step of 4 columns: A operand rows of the leaf (clamped into range
+  // and masked unless FULL), B operand from x or the level's projections.
+  // Four steps' loads are issued before their MFMAs so several are in flight.
+  auto kstep = [&](bool tr, const S* Am, int64_t ldA, int kcol, int kend, const double* Bm, int64_t ldB, int kofs,
+                   double (&av)[4], double (&bv)[NCB]) {
+    const int kk = kcol + lq, kc = FULL ? kk : min(kk, kend - 1);
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
-      const int row = wr0 + 16 * rb + li, rc = min(row, m - 1);
-      const double v = TRANS ? (double)D[o + kc + (int64_t)rc * ldd] : (double)D[o + rc + (int64_t)kc * ldd];
-      av[rb] = (row < m && kk < m) ? v : 0.0;
+      const int row = wr0 + 16 * rb + li, rc = FULL ? row : min(row, m - 1);
+      const double v = tr ? (double)Am[o + kc + (int64_t)rc * ldA] : (double)Am[o + rc + (int64_t)kc * ldA];
+      av[rb] = (FULL || (row < m && kk < kend)) ? v : 0.0;
     }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
       const int col = c0 + 16 * cb + li;
-      const double v = X[o + kc + (int64_t)min(col, nrhs - 1) * ldx];
-      bv[cb] = (kk < m && col < nrhs) ? v : 0.0;
+      const double v = Bm[kofs + kc + (int64_t)min(col, nrhs - 1) * ldB];
+      bv[cb] = ((FULL || kk < kend) && col < nrhs) ? v : 0.0;
     }
+  };
+  auto run = [&](bool tr, const S* Am, int64_t ldA, int kbeg, int kend, const double* Bm, int64_t ldB, int kofs) {
+    int k0 = kbeg;
+    for (; k0 + 16 <= kend; k0 += 16) {
+      double av[4][4], bv[4][NCB];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+      for (int u = 0; u < 4; ++u) kstep(tr, Am, ldA, k0 + 4 * u, kend, Bm, ldB, kofs, av[u], bv[u]);
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mma64(av[rb], bv[cb], acc[rb][cb]);
-  }
-  // low-rank blocks of every level
-  for (int l = 1; l <= L; ++l) {
-    const int cl0 = rpre[l - 1], cl1 = rpre[l];
-    if (cl1 == cl0) continue;
-    const int node = leaf >> (L - l);
-    const double* Sg = tree + tree_slot(l, node ^ 1) * R * nrhs;
-#pragma unroll 4
-    for (int k0 = cl0; k0 < cl1; k0 += 4) {
-      const int kk = k0 + lq, kc = min(kk, cl1 - 1);
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mma64(av[u][rb], bv[u][cb], acc[rb][cb]);
+    }
+    for (; k0 < kend; k0 += 4) {
       double av[4], bv[NCB];
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
-        const int row = wr0 + 16 * rb + li;
-        const double v = (double)Ua[o + min(row, m - 1) + (int64_t)kc * lda];
-        av[rb] = (row < m && kk < cl1) ? v : 0.0;
-      }
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        const int col = c0 + 16 * cb + li;
-        const double v = Sg[kc + (int64_t)min(col, nrhs - 1) * R];
-        bv[cb] = (kk < cl1 && col < nrhs) ? v : 0.0;
-      }
+      kstep(tr, Am, ldA, k0, kend, Bm, ldB, kofs, av, bv);
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mma64(av[rb], bv[cb], acc[rb][cb]);
     }
+  };
+  // leaf block: rows of x are the leaf's rows
+  run(TRANS, D, ldd, 0, m, X + o, ldx, 0);
+  // low-rank blocks of every level: the sibling's projections V^T x
+  for (int l = 1; l <= L; ++l) {
+    const int cl0 = rpre[l - 1], cl1 = rpre[l];
+    if (cl1 == cl0) continue;
+    const int node = leaf >> (L - l);
+    run(false, Ua, lda, cl0, cl1, tree + tree_slot(l, node ^ 1) * R * nrhs, R, 0);
   }
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
@@ -121,27 +119,32 @@ __global__ __launch_bounds__(kMvThreads) void matvec_apply_kernel(
 template <typename S>
 hipError_t launch_matvec_apply(hipStream_t s, int trans, int nleaf, int L, const int64_t* d_leaf_off,
                                const int32_t* d_rpre, int R, const S* D, int64_t ldd, const S* Ua, int64_t lda,
-                               const double* X, int64_t ldx, const double* tree, double* Y, int64_t ldy, int nrhs) {
+                               const double* X, int64_t ldx, const double* tree, double* Y, int64_t ldy, int nrhs,
+                               int full) {
   if (nleaf == 0 || nrhs == 0) return hipSuccess;
   const int zchunks = (nrhs + 63) / 64;
   dim3 grid((unsigned)(nleaf * zchunks));
-#define HODLR_MV(TR, NC)                                                                                             \
-  hipLaunchKernelGGL((matvec_apply_kernel<S, TR, NC>), grid, dim3(kMvThreads), 0, s, d_leaf_off, L, d_rpre, R, D, ldd, \
-                     Ua, lda, X, ldx, tree, Y, ldy, nrhs, zchunks)
+#define HODLR_MV(TR, NC)                                                                                        \
+  if (full)                                                                                                       \
+    hipLaunchKernelGGL((matvec_apply_kernel<S, TR, NC, true>), grid, dim3(kMvThreads), 0, s, d_leaf_off, L, d_rpre, \
+                       R, D, ldd, Ua, lda, X, ldx, tree, Y, ldy, nrhs, zchunks);                                   \
+  else                                                                                                            \
+    hipLaunchKernelGGL((matvec_apply_kernel<S, TR, NC, false>), grid, dim3(kMvThreads), 0, s, d_leaf_off, L, d_rpre, \
+                       R, D, ldd, Ua, lda, X, ldx, tree, Y, ldy, nrhs, zchunks)
   if (trans) {
-    if (nrhs <= 16) HODLR_MV(1, 1); else HODLR_MV(1, 4);
+    if (nrhs <= 16) { HODLR_MV(1, 1); } else { HODLR_MV(1, 4); }
   } else {
-    if (nrhs <= 16) HODLR_MV(0, 1); else HODLR_MV(0, 4);
+    if (nrhs <= 16) { HODLR_MV(0, 1); } else { HODLR_MV(0, 4); }
   }
 #undef HODLR_MV
   return hipGetLastError();
 }
 template hipError_t launch_matvec_apply<double>(hipStream_t, int, int, int, const int64_t*, const int32_t*, int,
                                                 const double*, int64_t, const double*, int64_t, const double*,
-                                                int64_t, const double*, double*, int64_t, int);
+                                                int64_t, const double*, double*, int64_t, int, int);
 template hipError_t launch_matvec_apply<float>(hipStream_t, int, int, int, const int64_t*, const int32_t*, int,
                                                const float*, int64_t, const float*, int64_t, const double*, int64_t,
-                                               const double*, double*, int64_t, int);
+                                               const double*, double*, int64_t, int, int);
 
 // ---------------------------------------------------------------------------
 // gradients
