@@ -180,7 +180,7 @@ constexpr int kZtLd = 17;  // padded row length of the per-wave 16 x 16 turn-aro
 
 template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE>
 __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level_pass_fast_kernel(
-    const Tile* __restrict__ tiles, int zchunks, int zc_base, int bchunks, TZ* Z, int64_t ldz, int nz, const SA* __restrict__ A1,
+    const Tile* __restrict__ tiles, int zchunks, int c_base, int bchunks, TZ* Z, int64_t ldz, int nz, const SA* __restrict__ A1,
     int64_t lda, const TZ* __restrict__ W, int64_t w_ld, int64_t w_pstride, int node_shift,
     const SB* __restrict__ B1, int64_t ldb, int kb_total, TZ* __restrict__ P, GroupStrides gs) {
   using M = Mfma<TZ>;
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
   const int nrows = tl.nrows;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lq = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: addresses stay scalar
-  const int c0 = (zc_base + zchunk) * kCw;
+  const int c0 = c_base + zchunk * kCw;
   const int ncz = MODE == 0 ? kCw : min(kCw, nz - c0);  // valid columns of this chunk
   const int wr0 = 64 * w;
   const int nrb = max(0, min(4, (nrows - wr0) >> 4));  // 16-row blocks of this wave
@@ -362,41 +362,57 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
   }
 }
 
-template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB>
-static hipError_t launch_fast(hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z, int64_t ldz,
-                              const SA* A1, int64_t lda, const TZ* W, int64_t w_ld, int64_t w_pstride,
-                              int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P, GroupStrides gs) {
+template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE>
+static hipError_t launch_part(hipStream_t s, int ntiles, int zchunks, int c_base, int nz, int bchunks,
+                              const Tile* tiles, TZ* Z, int64_t ldz, const SA* A1, int64_t lda, const TZ* W,
+                              int64_t w_ld, int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
+                              GroupStrides gs) {
+  if (zchunks == 0) return hipSuccess;
   constexpr int kCw = 16 * NCB;
   const size_t smem_main = sizeof(TZ) * (kCw * 4 * (size_t)NKS + 4 * (16 * kZtLd + 16 * (16 * MB + 1)));
   const size_t smem_red = MB > 0 ? sizeof(TZ) * 2 * 16 * MB * kCw : 0;
   const size_t smem = smem_main > smem_red ? smem_main : smem_red;
-  // whole chunks in one launch, the ragged last chunk (if any) in a second
-  const int nfull = nz / kCw, rest = nz % kCw;
-  for (int part = 0; part < 2; ++part) {
-    const int zchunks = part == 0 ? nfull : (rest ? 1 : 0);
-    if (zchunks == 0) continue;
-    const int64_t grid = (int64_t)ntiles * zchunks * bchunks;
-    if (grid > 0x7fffffff) return hipErrorInvalidValue;
-    auto k = part == 0 ? level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, 0>
-             : rest % 16 == 0 ? level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, 1>
-                              : level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, 2>;
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kLpThreads), smem, s, tiles, zchunks, part == 0 ? 0 : nfull,
-                       bchunks, Z, ldz, nz, A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P, gs);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  const int64_t grid = (int64_t)ntiles * zchunks * bchunks;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  auto k = level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, MODE>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kLpThreads), smem, s, tiles, zchunks, c_base, bchunks, Z, ldz, nz,
+                     A1, lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P, gs);
+  return hipGetLastError();
 }
 
-template <typename TZ, typename SA, typename SB, int MB, int NCB>
+// Columns of Z in up to three launches: chunks of 64, then the whole 16-column
+// blocks that are left as one narrower chunk, then a last partial block
+// (per-lane column test).  Every launch computes only columns that exist.
+template <typename TZ, typename SA, typename SB, int MB, int NKS>
+static hipError_t launch_fast(hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z, int64_t ldz,
+                              const SA* A1, int64_t lda, const TZ* W, int64_t w_ld, int64_t w_pstride,
+                              int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P, GroupStrides gs) {
+  const int n64 = nz / 64, nb = (nz % 64) / 16, tail = nz % 16;
+  hipError_t e = launch_part<TZ, SA, SB, MB, NKS, 4, 0>(s, ntiles, n64, 0, nz, bchunks, tiles, Z, ldz, A1, lda, W,
+                                                         w_ld, w_pstride, node_shift, B1, ldb, kb, P, gs);
+  if (e != hipSuccess) return e;
+  const int cb = 64 * n64;
+#define HODLR_LPB(NCBV)                                                                                          \
+  e = launch_part<TZ, SA, SB, MB, NKS, NCBV, 0>(s, ntiles, 1, cb, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,  \
+                                                 w_pstride, node_shift, B1, ldb, kb, P, gs)
+  if (nb == 1) HODLR_LPB(1);
+  else if (nb == 2) HODLR_LPB(2);
+  else if (nb == 3) HODLR_LPB(3);
+#undef HODLR_LPB
+  if (e != hipSuccess) return e;
+  return launch_part<TZ, SA, SB, MB, NKS, 1, 2>(s, ntiles, tail ? 1 : 0, cb + 16 * nb, nz, bchunks, tiles, Z, ldz, A1,
+                                                lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P, gs);
+}
+
+template <typename TZ, typename SA, typename SB, int MB>
 static hipError_t launch_fast_nks(int nks, hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z,
                                   int64_t ldz, const SA* A1, int64_t lda, const TZ* W, int64_t w_ld,
                                   int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
                                   GroupStrides gs) {
 #define HODLR_LPF(NKSV)                                                                                       \
-  return launch_fast<TZ, SA, SB, MB, NKSV, NCB>(s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld, w_pstride, \
+  return launch_fast<TZ, SA, SB, MB, NKSV>(s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld, w_pstride,      \
                                                  node_shift, B1, ldb, kb, P, gs)
   switch (nks) {
     case 0: HODLR_LPF(0);
@@ -408,14 +424,14 @@ static hipError_t launch_fast_nks(int nks, hipStream_t s, int ntiles, int nz, in
 #undef HODLR_LPF
 }
 
-template <typename TZ, typename SA, typename SB, int NCB>
+template <typename TZ, typename SA, typename SB>
 static hipError_t launch_fast_all(hipStream_t s, int ntiles, const Tile* tiles, TZ* Z, int64_t ldz, int nz,
                                   const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld, int64_t w_pstride,
                                   int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P, GroupStrides gs) {
   const int bchunks = kb > 0 ? (kb + 63) / 64 : 1;
   const int nks = ka / 4;
 #define HODLR_LPM(MBV)                                                                                            \
-  return launch_fast_nks<TZ, SA, SB, MBV, NCB>(nks, s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,      \
+  return launch_fast_nks<TZ, SA, SB, MBV>(nks, s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,           \
                                                 w_pstride, node_shift, B1, ldb, kb, P, gs)
   switch (kb > 0 ? std::min(kb, 64) / 16 : 0) {
     case 0: HODLR_LPM(0);
@@ -443,11 +459,8 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int t
   const bool small_ld = 64 * ldz * (int64_t)sizeof(TZ) < (1ll << 31) && 64 * lda * (int64_t)sizeof(SA) < (1ll << 31) &&
                         64 * ldb * (int64_t)sizeof(SB) < (1ll << 31);
   if (tiles_aligned && small_ld && ka % 16 == 0 && kb % 16 == 0) {
-    if (nz <= 16)
-      return launch_fast_all<TZ, SA, SB, 1>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride, node_shift,
-                                            B1, ldb, kb, P, gs);
-    return launch_fast_all<TZ, SA, SB, 4>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride, node_shift,
-                                          B1, ldb, kb, P, gs);
+    return launch_fast_all<TZ, SA, SB>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride, node_shift, B1,
+                                       ldb, kb, P, gs);
   }
   const int mbn = kb > 0 ? (min(kb, 64) + 15) / 16 : 1;
   const size_t smem_red = kb > 0 ? sizeof(TZ) * 4 * 16 * mbn * 64 : 0;
