@@ -90,8 +90,13 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
           const int col = 16 * cb + li;
           acc[q][cb][t] = (row < m && col < cw) ? (T)D[o + pm[row] + (int64_t)(c0 + col) * ldd] : T(0);
         }
-    // 2. sweep with the L blocks of the earlier chunks
+    // 2. sweep with the L blocks of the earlier chunks; their diagonal-block
+    // inverses are staged in LDS first (the panel buffer is free until the
+    // panel), so the owner's step waits on no global load
     const int nk = 2 * c;
+    T* ILs = stage;
+    for (int e = tid; e < nk * 256; e += kLuThreads) ILs[e] = IL[e];
+    __syncthreads();
     for (int k = 0; k < nk; ++k) {
       T* xb = xk[k & 1];
       if ((k & 3) == w) {
@@ -102,28 +107,28 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
             for (int cb = 0; cb < 2; ++cb) {
               V nv = vzero<V>();
 #pragma unroll
-              for (int t = 0; t < 4; ++t) nv = M::mma(IL[k * 256 + li * 16 + M::crow(lq, t)], acc[q][cb][t], nv);
+              for (int t = 0; t < 4; ++t) nv = M::mma(ILs[k * 256 + li * 16 + M::crow(lq, t)], acc[q][cb][t], nv);
               acc[q][cb] = nv;
 #pragma unroll
               for (int t = 0; t < 4; ++t) xb[M::crow(lq, t) * kCW + 16 * cb + li] = nv[t];
             }
           }
       }
-      // operands of this step's update are independent of X_k: load them before the barrier
+      // operands of this step's update are independent of X_k: load them
+      // before the barrier (rows clamped in range, used only by active blocks)
       T av[4][4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int b = 4 * q + w;
-        const int prow = pm[min(16 * b + li, 255)];
+        const int b = min(4 * q + w, nbk - 1);
+        const int prow = pm[16 * b + li];
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-          av[q][ks] = (b > k && b < nbk) ? -F[prow + (int64_t)(16 * k + 4 * ks + lq) * ldl] : T(0);
+        for (int ks = 0; ks < 4; ++ks) av[q][ks] = -F[prow + (int64_t)(16 * k + 4 * ks + lq) * ldl];
       }
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int b = 4 * q + w;
-        if (b > k && b < nbk) {
+        if (b > k && b < nbk) {  // uniform
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
