@@ -34,17 +34,17 @@ namespace hodlr {
 constexpr int kLuThreads = 256;
 constexpr int kCW = 32;  // chunk (panel) width
 
-template <typename T, typename S>
-__global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const int64_t* __restrict__ leaf_off,
+template <typename T, typename S, int CW>
+__global__ __launch_bounds__(kLuThreads, CW == 16 ? 3 : 2) void leaf_lu_kernel(int ldl, const int64_t* __restrict__ leaf_off,
                                                              const S* __restrict__ D, int64_t ldd, T* lu,
                                                              int32_t* __restrict__ piv, int32_t* __restrict__ perm,
                                                              T* __restrict__ udinv, T* invl,
                                                              unsigned long long* info) {
   using M = Mfma<T>;
   using V = typename M::V;
-  __shared__ T stage[256 * kCW];  // panel rows, row-major [row][32]
-  __shared__ T xk[2][16 * kCW];   // published X_k [row][col]
-  __shared__ T crow_[2][4][kCW];  // per wave: the row of its best pivot candidate
+  __shared__ T stage[256 * CW];  // panel rows, row-major [row][32]
+  __shared__ T xk[2][16 * CW];   // published X_k [row][col]
+  __shared__ T crow_[2][4][CW];  // per wave: the row of its best pivot candidate
   __shared__ T cval[2][4];        // per wave: |candidate|
   __shared__ int ckey[2][4];      // per wave: candidate position (INT_MAX: none)
   __shared__ int pm[256];         // position -> original (leaf-local) row
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
   T* IL = invl + (int64_t)a * 2 * (ldl / 16) * 256;
   int32_t* pv = piv + (int64_t)a * ldl;
   const int nbk = (m + 15) >> 4;
-  const int nch = (m + kCW - 1) / kCW;
+  const int nch = (m + CW - 1) / CW;
 
   for (int i = tid0; i < 256; i += kLuThreads) pm[i] = i;
   // zero padding outside m x m (never touched by the factorization)
@@ -76,14 +76,14 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
     asm volatile("" : "+v"(tid));
     asm volatile("" : "+s"(w));
     const int lane = tid & 63, li = lane & 15, lq = lane >> 4;
-    const int c0 = kCW * c;
-    const int cw = min(kCW, m - c0);
+    const int c0 = CW * c;
+    const int cw = min(CW, m - c0);
     // 1. load the chunk in the current row order
-    V acc[4][2];
+    V acc[4][CW / 16];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int cb = 0; cb < CW / 16; ++cb)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int row = 16 * (4 * q + w) + M::crow(lq, t);
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
     // 2. sweep with the L blocks of the earlier chunks; their diagonal-block
     // inverses are staged in LDS first (the panel buffer is free until the
     // panel), so the owner's step waits on no global load
-    const int nk = 2 * c;
+    const int nk = (CW / 16) * c;
     T* ILs = stage;
     for (int e = tid; e < nk * 256; e += kLuThreads) ILs[e] = IL[e];
     __syncthreads();
@@ -104,13 +104,13 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
         for (int q = 0; q < 4; ++q)
           if (4 * q + w == k) {
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
+            for (int cb = 0; cb < CW / 16; ++cb) {
               V nv = vzero<V>();
 #pragma unroll
               for (int t = 0; t < 4; ++t) nv = M::mma(ILs[k * 256 + li * 16 + M::crow(lq, t)], acc[q][cb][t], nv);
               acc[q][cb] = nv;
 #pragma unroll
-              for (int t = 0; t < 4; ++t) xb[M::crow(lq, t) * kCW + 16 * cb + li] = nv[t];
+              for (int t = 0; t < 4; ++t) xb[M::crow(lq, t) * CW + 16 * cb + li] = nv[t];
             }
           }
       }
@@ -132,8 +132,8 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-              acc[q][cb] = M::mma(av[q][ks], xb[(4 * ks + lq) * kCW + 16 * cb + li], acc[q][cb]);
+            for (int cb = 0; cb < CW / 16; ++cb)
+              acc[q][cb] = M::mma(av[q][ks], xb[(4 * ks + lq) * CW + 16 * cb + li], acc[q][cb]);
         }
       }
     }
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int cb = 0; cb < CW / 16; ++cb)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int row = 16 * (4 * q + w) + M::crow(lq, t);
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
             if (row < c0) {
               if (col < cw) F[pm[row] + (int64_t)(c0 + col) * ldl] = acc[q][cb][t];
             } else {
-              stage[(row - c0) * kCW + col] = acc[q][cb][t];
+              stage[(row - c0) * CW + col] = acc[q][cb][t];
             }
           }
         }
@@ -161,11 +161,11 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
     int mypos = tid;
     bool done = false;
     const int orig = own ? pm[c0 + tid] : 0;
-    T r[kCW];
+    T r[CW];
 #pragma unroll
-    for (int cc = 0; cc < kCW; ++cc) r[cc] = own ? stage[tid * kCW + cc] : T(0);
+    for (int cc = 0; cc < CW; ++cc) r[cc] = own ? stage[tid * CW + cc] : T(0);
 #pragma unroll
-    for (int j = 0; j < kCW; ++j) {
+    for (int j = 0; j < CW; ++j) {
       if (j < cw) {
         // one barrier per column: each wave publishes its best candidate (value,
         // position, whole row); every thread then picks the winner of the four
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
         v = vmax;
         if (cand && mypos == key) {
 #pragma unroll
-          for (int cc = 0; cc < kCW; ++cc) crow_[sb][w][cc] = r[cc];
+          for (int cc = 0; cc < CW; ++cc) crow_[sb][w][cc] = r[cc];
         }
         if (lane == 0) {
           cval[sb][w] = v;
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
               const T l = r[j] * (T(1) / pivot);
               r[j] = l;
 #pragma unroll
-              for (int cc = j + 1; cc < kCW; ++cc) r[cc] -= l * prow[cc];
+              for (int cc = j + 1; cc < CW; ++cc) r[cc] -= l * prow[cc];
             }
           }
         }
@@ -221,11 +221,11 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
     T* dblk = stage;  // [32][32] row-major; the panel no longer reads stage
     if (own) {
 #pragma unroll
-      for (int cc = 0; cc < kCW; ++cc)
+      for (int cc = 0; cc < CW; ++cc)
         if (cc < cw) F[orig + (int64_t)(c0 + cc) * ldl] = r[cc];
-      if (mypos < kCW) {
+      if (mypos < CW) {
 #pragma unroll
-        for (int cc = 0; cc < kCW; ++cc) dblk[mypos * kCW + cc] = r[cc];
+        for (int cc = 0; cc < CW; ++cc) dblk[mypos * CW + cc] = r[cc];
       }
     }
     __syncthreads();
@@ -237,17 +237,17 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
       const int half = (tid >> 4) & 1;
       int cc = tid & 15;
       asm volatile("" : "+v"(cc));  // keeps the identity columns from being hoisted out of the chunk loop
-      const int kb = 2 * c + half;
+      const int kb = (CW / 16) * c + half;
       const int g0 = 16 * kb;
-      const T* Bk = dblk + (16 * half) * kCW + 16 * half;  // element (i, j) at Bk[i * kCW + j]
-      if (kb < nbk) {
+      const T* Bk = dblk + (16 * half) * CW + 16 * half;  // element (i, j) at Bk[i * CW + j]
+      if (half < CW / 16 && kb < nbk) {
         T x[16];
         if (tid < 32) {
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             T sacc = (i == cc) ? T(1) : T(0);
 #pragma unroll
-            for (int jj = 0; jj < i; ++jj) sacc -= ((g0 + i < m) ? Bk[i * kCW + jj] : T(0)) * x[jj];
+            for (int jj = 0; jj < i; ++jj) sacc -= ((g0 + i < m) ? Bk[i * CW + jj] : T(0)) * x[jj];
             x[i] = (i >= cc) ? sacc : T(0);
           }
 #pragma unroll
@@ -258,17 +258,17 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
             T sacc = (i == cc) ? T(1) : T(0);
 #pragma unroll
             for (int jj = i + 1; jj < 16; ++jj)
-              sacc -= ((g0 + i < m && g0 + jj < m) ? Bk[i * kCW + jj] : T(0)) * x[jj];
-            const T d = (g0 + i < m) ? Bk[i * kCW + i] : T(1);
+              sacc -= ((g0 + i < m && g0 + jj < m) ? Bk[i * CW + jj] : T(0)) * x[jj];
+            const T d = (g0 + i < m) ? Bk[i * CW + i] : T(1);
             x[i] = (i <= cc) ? sacc / d : T(0);
           }
 #pragma unroll
           for (int i = 0; i < 16; ++i) IL[(ldl / 16 + kb) * 256 + i * 16 + cc] = x[i];
         }
       }
-    } else if (tid < 64 + kCW && c0 + tid - 64 < ldl) {
+    } else if (tid < 64 + CW && c0 + tid - 64 < ldl) {
       const int j = tid - 64;
-      udinv[(int64_t)a * ldl + c0 + j] = (j < cw) ? T(1) / dblk[j * kCW + j] : T(1);
+      udinv[(int64_t)a * ldl + c0 + j] = (j < cw) ? T(1) / dblk[j * CW + j] : T(1);
     }
     __syncthreads();
   }
@@ -279,17 +279,17 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
   if (__syncthreads_or(moved)) {
     const int src = tid < m ? pm[tid] : tid;
     for (int g = 0; g < nch; ++g) {
-      T r[kCW];
+      T r[CW];
 #pragma unroll
-      for (int cc = 0; cc < kCW; ++cc) {
-        const int col = min(kCW * g + cc, m - 1);
+      for (int cc = 0; cc < CW; ++cc) {
+        const int col = min(CW * g + cc, m - 1);
         r[cc] = F[min(src, ldl - 1) + (int64_t)col * ldl];
       }
       __syncthreads();
       if (moved) {
 #pragma unroll
-        for (int cc = 0; cc < kCW; ++cc)
-          if (kCW * g + cc < m) F[tid + (int64_t)(kCW * g + cc) * ldl] = r[cc];
+        for (int cc = 0; cc < CW; ++cc)
+          if (CW * g + cc < m) F[tid + (int64_t)(CW * g + cc) * ldl] = r[cc];
       }
       __syncthreads();
     }
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kLuThreads, 2) void leaf_lu_kernel(int ldl, const i
   for (int i = tid; i < ldl; i += kLuThreads) {
     pmo[i] = i < m ? pm[i] : i;
     if (i >= m) pv[i] = i;
-    if (i >= nch * kCW) udinv[(int64_t)a * ldl + i] = T(1);  // beyond the last chunk of a short leaf
+    if (i >= nch * CW) udinv[(int64_t)a * ldl + i] = T(1);  // beyond the last chunk of a short leaf
   }
 }
 
@@ -307,8 +307,8 @@ hipError_t launch_leaf_lu(hipStream_t s, int nleaf, int ldl, const int64_t* d_le
                           T* lu, int32_t* piv, int32_t* perm, T* udinv, T* invl, unsigned long long* info) {
   if (nleaf == 0) return hipSuccess;
   if (ldl % 16 || ldl > 256) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((leaf_lu_kernel<T, S>), dim3(nleaf), dim3(kLuThreads), 0, s, ldl, d_leaf_off, D, ldd, lu, piv,
-                     perm, udinv, invl, info);
+  hipLaunchKernelGGL((leaf_lu_kernel<T, S, kCW>), dim3(nleaf), dim3(kLuThreads), 0, s, ldl, d_leaf_off, D, ldd, lu,
+                     piv, perm, udinv, invl, info);
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ namespace hodlr {
 constexpr int kTsThreads = 256;
 constexpr int kTwLd = 17;  // padded row length of the owner's 16 x 16 turn-around buffer
 
-template <typename T, typename S, int TRANS, int NCB>
+template <typename T, typename S, int TRANS, int NQ, int NCB>
 __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int64_t* __restrict__ leaf_off,
                                                              int64_t ostride, int mfix, const T* __restrict__ lu,
                                                              const int32_t* __restrict__ perm,
@@ -34,8 +34,9 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
                                                              int64_t gsx) {
   using M = Mfma<T>;
   using V = typename M::V;
-  __shared__ T invA[16 * 256];     // inverse diagonal blocks of the current sweep, [kb][i][j]
-  __shared__ T xk[2][16 * 64];     // published block X_k: [row][col]
+  __shared__ T invA[4 * NQ * 256];  // inverse diagonal blocks of the current sweep, [kb][i][j]
+  constexpr int kCwT = 16 * NCB;     // columns of a chunk
+  __shared__ T xk[2][16 * kCwT];   // published block X_k: [row][col]
   __shared__ T tw[4][16 * kTwLd];  // per-wave turn-around of the owner's block
 
   const int lid = (int)xcd_remap(blockIdx.x, gridDim.x);
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
   T* Xb = X + group_row(o, gsx);
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lq = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int c0 = chunk * 64;
+  const int c0 = chunk * kCwT;
   const int nbk = (m + 15) >> 4;
   const T* F = lu + (int64_t)a * ldl * ldl;
   const int32_t* pm = perm + (int64_t)a * ldl;
@@ -79,9 +80,9 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
   // The chunk is held transposed: accumulator block (q, cb), register t holds
   // X(16 (4 q + w) + li, c0 + 16 cb + crow(lq, t)), so the 16 lanes of a row
   // group touch 16 consecutive rows of one column (whole 128-byte lines).
-  V acc[4][NCB];
+  V acc[NQ][NCB];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int row = 16 * (4 * q + w) + li;
     const int rowc = min(row, m - 1);
     const int src = TRANS ? rowc : pm[rowc];
@@ -110,16 +111,16 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
         nv = M::mma(twv[(4 * ks + lq) * kTwLd + li], invA[k * 256 + li * 16 + 4 * ks + lq], nv);
       acc[q][cb] = nv;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) xb[li * 64 + 16 * cb + M::crow(lq, t)] = nv[t];
+      for (int t = 0; t < 4; ++t) xb[li * kCwT + 16 * cb + M::crow(lq, t)] = nv[t];
     }
   };
   // B_b^T -= X_k^T M_bk^T on accumulator block q2
-  auto update = [&](int q2, const T (&av)[4][4], const T* xb) {
+  auto update = [&](int q2, const T (&av)[NQ][4], const T* xb) {
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
-        acc[q2][cb] = M::mma(xb[(4 * ks + lq) * 64 + 16 * cb + li], av[q2][ks], acc[q2][cb]);
+        acc[q2][cb] = M::mma(xb[(4 * ks + lq) * kCwT + 16 * cb + li], av[q2][ks], acc[q2][cb]);
   };
 
   // The steps are unrolled so that every block index is a compile-time
@@ -132,8 +133,8 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
       __syncthreads();
     }
 #pragma clang loop unroll(full)
-    for (int st = 0; st < 16; ++st) {
-      const int k = sweep == 0 ? st : 15 - st;
+    for (int st = 0; st < 4 * NQ; ++st) {
+      const int k = sweep == 0 ? st : 4 * NQ - 1 - st;
       if (k < nbk) {  // uniform
         const int q = k >> 2, wk = k & 3;
         // step index within the sweep decides the X buffer (sweep 1 starts at nbk - 1)
@@ -145,9 +146,9 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
         // the factor operands M(16 b + li, 16 k + 4 ks + lq) of this wave's blocks
         // on the far side of k do not depend on X_k: fetched before the barrier
         // (clamped in range, no branches)
-        T av[4][4];
+        T av[NQ][4];
 #pragma unroll
-        for (int q2 = 0; q2 < 4; ++q2) {
+        for (int q2 = 0; q2 < NQ; ++q2) {
           if (sweep == 0 ? q2 < q : q2 > q) continue;  // never on the far side: compile time
           const int b = min(4 * q2 + w, nbk - 1);
 #pragma unroll
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
           owner(qn, kn, xn);
         }
 #pragma unroll
-        for (int q2 = 0; q2 < 4; ++q2) {
+        for (int q2 = 0; q2 < NQ; ++q2) {
           if (sweep == 0 ? q2 < q : q2 > q) continue;
           const int b = 4 * q2 + w;
           const bool act = (sweep == 0 ? (q2 > q || w > wk) : (q2 < q || w < wk)) && b < nbk &&
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
 
   // store (the adjoint scatters rows through the permutation)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int row = 16 * (4 * q + w) + li;
     if (row < m) {
       const int dst = TRANS ? pm[row] : row;
@@ -202,18 +203,31 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
                               int64_t ldx, int ncols, int64_t gsb, int64_t gsx) {
   if (nblk == 0 || ncols == 0) return hipSuccess;
   if (ldl % 16 || ldl > 256) return hipErrorInvalidValue;
-  const int nchunks = (ncols + 63) / 64;
+  // blocks of at most 64 rows (coupling systems): one 16-row block per wave
+  // and chunks of 128 columns; otherwise four blocks per wave and 64 columns
+  const int nq = ldl <= 64 ? 1 : 4;
+  const int cw = nq == 1 ? (ncols > 64 ? 128 : ncols > 16 ? 64 : 16) : (ncols > 16 ? 64 : 16);
+  const int nchunks = (ncols + cw - 1) / cw;
   const int64_t grid = (int64_t)nblk * nchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-#define HODLR_TS(TR, NC)                                                                                  \
-  hipLaunchKernelGGL((trsm_kernel<T, S, TR, NC>), dim3((unsigned)grid), dim3(kTsThreads), 0, s, ldl, d_off, ostride, \
-                     mfix, lu, perm, dinv, B, ldb, X, ldx, ncols, nchunks, gsb, gsx)
-  // one 16-column block per chunk for narrow right-hand sides, four otherwise
-  if (trans) {
-    if (ncols <= 16) HODLR_TS(1, 1); else HODLR_TS(1, 4);
-  } else {
-    if (ncols <= 16) HODLR_TS(0, 1); else HODLR_TS(0, 4);
+#define HODLR_TS(TR, NQ, NC)                                                                                  \
+  hipLaunchKernelGGL((trsm_kernel<T, S, TR, NQ, NC>), dim3((unsigned)grid), dim3(kTsThreads), 0, s, ldl, d_off,     \
+                     ostride, mfix, lu, perm, dinv, B, ldb, X, ldx, ncols, nchunks, gsb, gsx)
+#define HODLR_TS_W(TR)                      \
+  if (nq == 1) {                            \
+    if (cw == 128) HODLR_TS(TR, 1, 8);      \
+    else if (cw == 64) HODLR_TS(TR, 1, 4);  \
+    else HODLR_TS(TR, 1, 1);                \
+  } else {                                  \
+    if (cw == 64) HODLR_TS(TR, 4, 4);       \
+    else HODLR_TS(TR, 4, 1);                \
   }
+  if (trans) {
+    HODLR_TS_W(1)
+  } else {
+    HODLR_TS_W(0)
+  }
+#undef HODLR_TS_W
 #undef HODLR_TS
   return hipGetLastError();
 }
