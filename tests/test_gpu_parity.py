@@ -287,3 +287,52 @@ def test_many_tiles_and_segments():
     assert _rel(X, O.solve(O.factor(H), B)) < 1e-12
     G = _from_dev(F.solve_adjoint(_to_dev(B)))
     assert O.relres(O.transpose(H), G, B) < 1e-13
+
+
+def test_full_size_bie_in_bench_configuration():
+    """The benchmark workload itself (Laplace double-layer BIE on the star
+    curve, N = 2^20, leaf 256, 12 levels, rank 32) in the launch configuration
+    that bench.py times.  Checked at full size by properties the oracle can
+    evaluate cheaply: the FP64 residual of the whole solve through the
+    oracle's own HODLR product (host, FP64), and Y_big on sampled rows, the
+    leftmost level-8 subtree (4096 rows), whose Y columns of levels 9..12
+    equal the Y of that subtree as a HODLR matrix of its own; the mixed path
+    must refine to a residual of 1e-10."""
+    _say("full-size BIE N=2^20: generating")
+    inp = W.make_config(2, device=DEV)
+    A = H_().HODLRMatrix.from_inputs(inp)
+    b = W.gaussian_rhs(inp.n, 1, seed=0, device=DEV)
+    F = H_().factor(A, "fp64")
+    x = F.solve(b)
+    Y = F.y_big()
+    torch.cuda.synchronize()
+    _say("full-size BIE: oracle checks")
+    H = O.from_inputs(inp)
+    bh = b.detach().cpu().numpy().T
+    xh = x.detach().cpu().numpy().T
+    relres = np.linalg.norm(bh - O.matvec(H, xh)) / np.linalg.norm(bh)
+    _say(f"full-size BIE FP64 relres {relres:.3e}")
+    assert relres < 1e-12
+    # sampled Y_big: the leftmost level-8 subtree
+    k = 8
+    Lsub = H.L - k
+    nsub = int(H.offsets[1 << Lsub])
+    c0 = int(sum(H.ranks[:k]))
+    Hs = O.Hodlr(H.offsets[: (1 << Lsub) + 1].copy(), list(H.ranks[k:]), H.D[:nsub].copy(), H.U[:nsub, c0:].copy(),
+                 H.V[:nsub, c0:].copy())
+    Ys = O.y_big(O.factor(Hs))
+    Yg = Y[c0:, :nsub].detach().cpu().numpy().T
+    for lv in range(1, Lsub + 1):
+        a0, a1 = Hs.colrange(lv)
+        err = _rel(Yg[:, a0:a1], Ys[:, a0:a1])
+        _say(f"full-size BIE Y level {k + lv}: rel err {err:.3e}")
+        assert err < 1e-12
+    del F
+    F32 = H_().factor(A, "fp32")
+    stats = {}
+    x32 = F32.solve(b, refine=True, tol=1e-10, stats=stats)
+    x32h = x32.detach().cpu().numpy().T
+    relres32 = np.linalg.norm(bh - O.matvec(H, x32h)) / np.linalg.norm(bh)
+    _say(f"full-size BIE FP32+IR relres {relres32:.3e} after {stats.get('iters')} steps")
+    assert relres32 <= 1e-10
+    assert _rel(x32h, xh) < 1e-10
