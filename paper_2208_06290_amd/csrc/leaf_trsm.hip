@@ -22,11 +22,10 @@
 
 namespace hodlr {
 
-constexpr int kTsThreads = 256;
 constexpr int kTwLd = 17;  // padded row length of the owner's 16 x 16 turn-around buffer
 
-template <typename T, typename S, int TRANS, int NQ, int NCB>
-__global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int64_t* __restrict__ leaf_off,
+template <typename T, typename S, int TRANS, int NW, int NQ, int NCB>
+__global__ __launch_bounds__(64 * NW, 8 / NW) void trsm_kernel(int ldl, const int64_t* __restrict__ leaf_off,
                                                              int64_t ostride, int mfix, const T* __restrict__ lu,
                                                              const int32_t* __restrict__ perm,
                                                              const T* __restrict__ dinv, const S* B, int64_t ldb,
@@ -34,10 +33,12 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
                                                              int64_t gsx) {
   using M = Mfma<T>;
   using V = typename M::V;
-  __shared__ T invA[4 * NQ * 256];  // inverse diagonal blocks of the current sweep, [kb][i][j]
+  constexpr int kThreads = 64 * NW;
+  constexpr int kBlocks = NW * NQ;  // 16-row blocks of a block (row block b is owned by wave b % NW)
+  __shared__ T invA[kBlocks * 256];  // inverse diagonal blocks of the current sweep, [kb][i][j]
   constexpr int kCwT = 16 * NCB;     // columns of a chunk
   __shared__ T xk[2][16 * kCwT];   // published block X_k: [row][col]
-  __shared__ T tw[4][16 * kTwLd];  // per-wave turn-around of the owner's block
+  __shared__ T tw[NW][16 * kTwLd];  // per-wave turn-around of the owner's block
 
   const int lid = (int)xcd_remap(blockIdx.x, gridDim.x);
   const int a = lid / nchunks;
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
   auto stage_inv = [&](int sweep) {
     const int which = TRANS ? 1 - sweep : sweep;
     const T* src = DI + (int64_t)which * nbd * 256;
-    for (int e = tid; e < nbk * 256; e += kTsThreads) {
+    for (int e = tid; e < nbk * 256; e += kThreads) {
       const int kb = e >> 8, i = (e >> 4) & 15, j = e & 15;
       invA[e] = TRANS ? src[kb * 256 + j * 16 + i] : src[e];
     }
@@ -78,12 +79,12 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
   stage_inv(0);
 
   // The chunk is held transposed: accumulator block (q, cb), register t holds
-  // X(16 (4 q + w) + li, c0 + 16 cb + crow(lq, t)), so the 16 lanes of a row
+  // X(16 (NW q + w) + li, c0 + 16 cb + crow(lq, t)), so the 16 lanes of a row
   // group touch 16 consecutive rows of one column (whole 128-byte lines).
   V acc[NQ][NCB];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const int row = 16 * (4 * q + w) + li;
+    const int row = 16 * (NW * q + w) + li;
     const int rowc = min(row, m - 1);
     const int src = TRANS ? rowc : pm[rowc];
 #pragma unroll
@@ -133,10 +134,10 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
       __syncthreads();
     }
 #pragma clang loop unroll(full)
-    for (int st = 0; st < 4 * NQ; ++st) {
-      const int k = sweep == 0 ? st : 4 * NQ - 1 - st;
+    for (int st = 0; st < kBlocks; ++st) {
+      const int k = sweep == 0 ? st : kBlocks - 1 - st;
       if (k < nbk) {  // uniform
-        const int q = k >> 2, wk = k & 3;
+        const int q = k / NW, wk = k % NW;
         // step index within the sweep decides the X buffer (sweep 1 starts at nbk - 1)
         const int sidx = sweep == 0 ? k : nbk - 1 - k;
         T* xb = xk[sidx & 1];
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
 #pragma unroll
         for (int q2 = 0; q2 < NQ; ++q2) {
           if (sweep == 0 ? q2 < q : q2 > q) continue;  // never on the far side: compile time
-          const int b = min(4 * q2 + w, nbk - 1);
+          const int b = min(NW * q2 + w, nbk - 1);
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
             const int i = 16 * b + li, j = 16 * k + 4 * ks + lq;
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
         // X_next at once, so the next step starts without waiting for it
         const int kn = sweep == 0 ? k + 1 : k - 1;
         const bool nxt = sweep == 0 ? kn < nbk : kn >= 0;
-        const int qn = kn >> 2, wn = kn & 3;
+        const int qn = kn / NW, wn = kn % NW;
         const bool la = nxt && w == wn;  // uniform
         if (la) {
           update(qn, av, xb);
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
 #pragma unroll
         for (int q2 = 0; q2 < NQ; ++q2) {
           if (sweep == 0 ? q2 < q : q2 > q) continue;
-          const int b = 4 * q2 + w;
+          const int b = NW * q2 + w;
           const bool act = (sweep == 0 ? (q2 > q || w > wk) : (q2 < q || w < wk)) && b < nbk &&
                            !(la && q2 == qn);  // uniform
           if (act) update(q2, av, xb);
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(kTsThreads, 2) void trsm_kernel(int ldl, const int6
   // store (the adjoint scatters rows through the permutation)
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const int row = 16 * (4 * q + w) + li;
+    const int row = 16 * (NW * q + w) + li;
     if (row < m) {
       const int dst = TRANS ? pm[row] : row;
 #pragma unroll
@@ -210,17 +211,19 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
   const int nchunks = (ncols + cw - 1) / cw;
   const int64_t grid = (int64_t)nblk * nchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-#define HODLR_TS(TR, NQ, NC)                                                                                  \
-  hipLaunchKernelGGL((trsm_kernel<T, S, TR, NQ, NC>), dim3((unsigned)grid), dim3(kTsThreads), 0, s, ldl, d_off,     \
+#define HODLR_TS(TR, NW, NQ, NC)                                                                               \
+  hipLaunchKernelGGL((trsm_kernel<T, S, TR, NW, NQ, NC>), dim3((unsigned)grid), dim3(64 * NW), 0, s, ldl, d_off,    \
                      ostride, mfix, lu, perm, dinv, B, ldb, X, ldx, ncols, nchunks, gsb, gsx)
-#define HODLR_TS_W(TR)                      \
-  if (nq == 1) {                            \
-    if (cw == 128) HODLR_TS(TR, 1, 8);      \
-    else if (cw == 64) HODLR_TS(TR, 1, 4);  \
-    else HODLR_TS(TR, 1, 1);                \
-  } else {                                  \
-    if (cw == 64) HODLR_TS(TR, 4, 4);       \
-    else HODLR_TS(TR, 4, 1);                \
+  // up to 64 rows: 4 waves, one block each; up to 256 rows: 4 waves with four
+  // blocks each for wide right-hand sides, 8 waves with two each for narrow ones
+#define HODLR_TS_W(TR)                         \
+  if (nq == 1) {                               \
+    if (cw == 128) HODLR_TS(TR, 4, 1, 8);      \
+    else if (cw == 64) HODLR_TS(TR, 4, 1, 4);  \
+    else HODLR_TS(TR, 4, 1, 1);                \
+  } else {                                     \
+    if (cw == 64) HODLR_TS(TR, 4, 4, 4);       \
+    else HODLR_TS(TR, 8, 2, 1);                \
   }
   if (trans) {
     HODLR_TS_W(1)
