@@ -37,7 +37,7 @@ PEAK = dict(hbm=8.0e12, f64=78.6e12, f32=157.3e12, bf16=2.5e15)
 # reads back; summary and commands in profiles/level_pass_traffic_n1m_fp64.md).
 # It is reported only while the kernel source is the one it was measured on.
 LEVEL_PASS_TRAFFIC = dict(
-    source_sha256="02658ca76f654d868ce2600379a00d3340be48ece16050a8d90b4e1155b88651",
+    source_sha256="b338bd377a08a7f48f72049580363a39f1072acf4c3daa5159e457467dc2f374",
     n=1 << 20, leaf=256, rank=32, bytes_per_launch=4.26e9)
 
 
