@@ -6,12 +6,16 @@
 // The products V^T Y arrive as per-tile partial sums (level pass) or as
 // segment sums of them; they are summed here in fixed order.
 //
-// couple_factor: one workgroup per parent; K is formed in LDS and LU-factored
-//   with partial pivoting by one wave (largest magnitude, lowest row on ties)
-//   while the other waves sum the right-hand sides
-//   [V_a^T Y_big(I_a, 1:R_l); V_b^T Y_big(I_b, 1:R_l)] of eq. "e:node1" into
-//   W; the MFMA block solver then overwrites W with K^{-1} W.  The LU of K is stored zero-padded to kp x kp (kp = 2r
-//   rounded up to 16) so the block solver needs no bounds checks.
+// couple_factor: one workgroup per parent; K is formed in LDS from the
+//   children's reduced products, the right-hand sides
+//   [V_a^T Y_big(I_a, 1:R_l); V_b^T Y_big(I_b, 1:R_l)] of eq. "e:node1" are
+//   written to W, and K is LU-factored with partial pivoting (largest
+//   magnitude, lowest row on ties): by all four waves with K in registers
+//   when 2r <= 64, else by one wave in LDS.  The LU of K is stored
+//   zero-padded to kp x kp (kp = 2r rounded up to 16) so the block solver
+//   needs no bounds checks; couple_dinv then forms the inverted 16 x 16
+//   diagonal blocks of L and U, and the MFMA block solver overwrites W with
+//   K^{-1} W.
 // couple_solve: one wave per parent; w = K^{-1} [V_a^T x_a; V_b^T x_b]
 //   (eq. "e:node3") or the transposed solve used by the adjoint.
 // Lanes own rows of the right-hand side (2r <= 128 -> two rows per lane) and
@@ -243,7 +247,7 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp
                                                                    const int32_t* __restrict__ seg_start,
                                                                    T* __restrict__ Klu, int32_t* __restrict__ Kpiv,
                                                                    int32_t* __restrict__ Kperm,
-                                                                   T* __restrict__ Kud, T* __restrict__ Kinv,
+                                                                   T* __restrict__ Kud,
                                                                    T* __restrict__ W, unsigned long long* info,
                                                                    int level, int L) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -369,38 +373,45 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp
     Kperm[(int64_t)g * kp + i] = i < n2 ? sperm[i] : i;
     Kud[(int64_t)g * kp + i] = i < n2 ? T(1) / K[i + i * n2] : T(1);
   }
-  // inverses of the 16 x 16 diagonal blocks of L and U (padded part: identity) for the block solver
-  {
-    const int nbd = kp >> 4;
-    const int which = tid >> 7;  // 0: L, 1: U
-    const int kb = (tid >> 4) & 7, cc = tid & 15;
-    if (kb < nbd) {
-      const int g0 = 16 * kb;
-      auto Kel = [&](int i, int j) -> T { return (i < n2 && j < n2) ? K[i + j * n2] : T(0); };
-      T x[16];
-      if (which == 0) {
+}
+
+// Inverses of the 16 x 16 diagonal blocks of L and U of every factored K
+// (padded part: identity), for the block solver.  A kernel of its own: the
+// unrolled substitutions need many registers, which would cap the occupancy of
+// the factorization.  Thread (which, kb, cc) forms column cc of block kb.
+template <typename T>
+__global__ __launch_bounds__(kCfThreads) void couple_dinv_kernel(int n2, int kp, const T* __restrict__ Klu,
+                                                                 T* __restrict__ Kinv) {
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int nbd = kp >> 4;
+  const int which = tid >> 7;  // 0: L, 1: U
+  const int kb = (tid >> 4) & 7, cc = tid & 15;
+  if (kb >= nbd) return;
+  const int g0 = 16 * kb;
+  const T* Kg = Klu + (int64_t)g * kp * kp + g0 + (int64_t)g0 * kp;  // zero-padded kp x kp, col-major
+  auto Kel = [&](int i, int j) -> T { return Kg[i + j * kp]; };
+  T x[16];
+  if (which == 0) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          T sv = (i == cc) ? T(1) : T(0);
+    for (int i = 0; i < 16; ++i) {
+      T sv = (i == cc) ? T(1) : T(0);
 #pragma unroll
-          for (int jj = 0; jj < i; ++jj) sv -= Kel(g0 + i, g0 + jj) * x[jj];
-          x[i] = (i >= cc) ? sv : T(0);
-        }
-      } else {
+      for (int jj = 0; jj < i; ++jj) sv -= Kel(i, jj) * x[jj];
+      x[i] = (i >= cc) ? sv : T(0);
+    }
+  } else {
 #pragma unroll
-        for (int i = 15; i >= 0; --i) {
-          T sv = (i == cc) ? T(1) : T(0);
+    for (int i = 15; i >= 0; --i) {
+      T sv = (i == cc) ? T(1) : T(0);
 #pragma unroll
-          for (int jj = i + 1; jj < 16; ++jj) sv -= Kel(g0 + i, g0 + jj) * x[jj];
-          const T d = (g0 + i < n2) ? K[(g0 + i) * (n2 + 1)] : T(1);
-          x[i] = (i <= cc) ? sv / d : T(0);
-        }
-      }
-      T* dst = Kinv + ((int64_t)g * 2 + which) * nbd * 256 + kb * 256;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) dst[i * 16 + cc] = x[i];
+      for (int jj = i + 1; jj < 16; ++jj) sv -= Kel(i, jj) * x[jj];
+      const T d = (g0 + i < n2) ? Kel(i, i) : T(1);
+      x[i] = (i <= cc) ? sv / d : T(0);
     }
   }
+  T* dst = Kinv + ((int64_t)g * 2 + which) * nbd * 256 + kb * 256;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) dst[i * 16 + cc] = x[i];
 }
 
 template <typename T>
@@ -414,7 +425,10 @@ hipError_t launch_couple_factor(hipStream_t s, int nparents, int r, int kp, int 
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(nparents), dim3(kCfThreads), smem, s, r, kp, Rp, segs, d_seg_start, Klu, Kpiv, Kperm,
-                     Kud, Kinv, W, info, level, L);
+                     Kud, W, info, level, L);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(couple_dinv_kernel<T>, dim3(nparents), dim3(kCfThreads), 0, s, 2 * r, kp, (const T*)Klu, Kinv);
   return hipGetLastError();
 }
 template hipError_t launch_couple_factor<double>(hipStream_t, int, int, int, int, const double*, const int32_t*,
