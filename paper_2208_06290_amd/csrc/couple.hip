@@ -172,14 +172,15 @@ constexpr int kCfThreads = 256;
 // position on ties, a NaN counts as infinite) and publishes the multipliers
 // through LDS (double buffered: one barrier per step); every wave then takes
 // the pivot row from its own registers with readlane and updates its columns.
-// The step loop is not unrolled (the code runs a few times per workgroup:
-// straight-line code would be bound by instruction fetch); column j is picked
-// out of the registers with selects, so register indices stay compile-time
-// constants.  On return K holds L\U in pivoted order and spiv[j] the
-// LAPACK-style interchange of step j.
+// Steps run in blocks of 16 (the owner's column is then a compile-time
+// register index); a wave whose columns all lie left of the current block
+// has nothing to update, a wave right of it updates all 16 columns without
+// per-column tests.  On return K holds L\U in pivoted order, spiv[j] the
+// LAPACK-style interchange of step j and sperm[i] the original row at
+// position i.
 template <typename T>
-__device__ __forceinline__ void block_lu(T* K, int n2, int lane, int w, int* spiv, unsigned long long* info,
-                                         unsigned long long info_base) {
+__device__ __forceinline__ void block_lu(T* K, int n2, int lane, int w, int* spiv, int* sperm,
+                                         unsigned long long* info, unsigned long long info_base) {
   __shared__ T s_l[2][64];
   __shared__ int s_pl[2][2];  // pivot lane, pivot value nonzero
   T kc[16];
@@ -190,48 +191,59 @@ __device__ __forceinline__ void block_lu(T* K, int n2, int lane, int w, int* spi
   }
   int mypos = lane;
   bool done = lane >= n2;
-  for (int j = 0; j < n2; ++j) {
-    const int sb = j & 1;
-    if (w == (j >> 4)) {
-      const int jc = j & 15;
-      T kj = T(0);
+  const int nb = (n2 + 15) >> 4;
+  for (int jb = 0; jb < nb; ++jb) {
 #pragma unroll
-      for (int c = 0; c < 16; ++c) kj = (c == jc) ? kc[c] : kj;
-      T v = done ? T(-1) : fabs(kj);
-      if (!done && !(v == v)) v = T(INFINITY);
-      T vmax;
-      int bk;  // pivot position (uniform)
-      wave_argmax(v, done ? 0x7fffffff : mypos, vmax, bk);
-      const unsigned long long sel = __ballot(!done && mypos == bk);
-      const int plane = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(sel));
-      const T pv = bcast(kj, plane);
-      const bool nz = pv != T(0);
-      s_l[sb][lane] = (!done && lane != plane && nz) ? kj * (T(1) / pv) : T(0);
-      if (lane == 0) {
-        s_pl[sb][0] = plane;
-        s_pl[sb][1] = nz;
-        spiv[j] = bk;
-        if (!nz) atomicMin(info, info_base | (unsigned long long)j);
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = 16 * jb + jj;
+      if (j < n2) {  // uniform
+        const int sb = jj & 1;
+        if (w == jb) {
+          const T kj = kc[jj];
+          T v = done ? T(-1) : fabs(kj);
+          if (!done && !(v == v)) v = T(INFINITY);
+          T vmax;
+          int bk;  // pivot position (uniform)
+          wave_argmax(v, done ? 0x7fffffff : mypos, vmax, bk);
+          const unsigned long long sel = __ballot(!done && mypos == bk);
+          const int plane = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(sel));
+          const T pv = bcast(kj, plane);
+          const bool nz = pv != T(0);
+          s_l[sb][lane] = (!done && lane != plane && nz) ? kj * (T(1) / pv) : T(0);
+          if (lane == 0) {
+            s_pl[sb][0] = plane;
+            s_pl[sb][1] = nz;
+            spiv[j] = bk;
+            if (!nz) atomicMin(info, info_base | (unsigned long long)j);
+          }
+        }
+        __syncthreads();
+        const int plane = __builtin_amdgcn_readfirstlane(s_pl[sb][0]);
+        const bool nz = s_pl[sb][1] != 0;
+        const T l = s_l[sb][lane];
+        const bool me = lane == plane;
+        const bool upd = !done && !me && nz;
+        const int bk = __builtin_amdgcn_readfirstlane(__shfl(mypos, plane, 64));
+        if (!done && !me && mypos == j) mypos = bk;  // the row displaced by the interchange
+        if (me) {
+          done = true;
+          mypos = j;
+        }
+        if (w == jb) {
+          kc[jj] = upd ? l : kc[jj];
+#pragma unroll
+          for (int c = jj + 1; c < 16; ++c) {
+            const T pc = bcast(kc[c], plane);
+            kc[c] = upd ? kc[c] - l * pc : kc[c];
+          }
+        } else if (w > jb) {
+#pragma unroll
+          for (int c = 0; c < 16; ++c) {
+            const T pc = bcast(kc[c], plane);
+            kc[c] = upd ? kc[c] - l * pc : kc[c];
+          }
+        }
       }
-    }
-    __syncthreads();
-    const int plane = __builtin_amdgcn_readfirstlane(s_pl[sb][0]);
-    const bool nz = s_pl[sb][1] != 0;
-    const T l = s_l[sb][lane];
-    const bool me = lane == plane;
-    const bool upd = !done && !me && nz;
-    const int bk = __builtin_amdgcn_readfirstlane(__shfl(mypos, plane, 64));
-    if (!done && !me && mypos == j) mypos = bk;  // the row displaced by the interchange
-    if (me) {
-      done = true;
-      mypos = j;
-    }
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const int col = 16 * w + c;
-      const T pc = bcast(kc[c], plane);
-      const T nv = (col == j) ? l : kc[c] - l * pc;
-      kc[c] = (upd && col >= j) ? nv : kc[c];
     }
   }
   __syncthreads();  // every wave has read K before it is overwritten
@@ -240,6 +252,7 @@ __device__ __forceinline__ void block_lu(T* K, int n2, int lane, int w, int* spi
     const int col = 16 * w + c;
     if (lane < n2 && col < n2) K[mypos + col * n2] = kc[c];
   }
+  if (w == 0 && lane < n2) sperm[mypos] = lane;
 }
 
 template <typename T>
@@ -285,7 +298,7 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp
     }
   }
   if (n2 <= 64) {
-    block_lu(K, n2, lane, wid, spiv, info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16));
+    block_lu(K, n2, lane, wid, spiv, sperm, info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16));
   } else if (wid == 0) {
     // LU with partial pivoting by one wave (rows over lanes, no block barriers)
     for (int j = 0; j < n2; ++j) {
@@ -358,7 +371,7 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp
     const int i = e % kp, j = e / kp;
     Kg[e] = (i < n2 && j < n2) ? K[i + j * n2] : T(0);
   }
-  if (tid == 0) {
+  if (n2 > 64 && tid == 0) {  // (block_lu records the row order itself)
     for (int i = 0; i < n2; ++i) sperm[i] = i;
     for (int j = 0; j < n2; ++j) {
       int p = spiv[j];
