@@ -204,10 +204,11 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
                               int64_t ldx, int ncols, int64_t gsb, int64_t gsx) {
   if (nblk == 0 || ncols == 0) return hipSuccess;
   if (ldl % 16 || ldl > 256) return hipErrorInvalidValue;
-  // blocks of at most 64 rows (coupling systems): one 16-row block per wave
-  // and chunks of 128 columns; otherwise four blocks per wave and 64 columns
+  // blocks of at most 64 rows (coupling systems): one 16-row block per wave,
+  // chunks of 128 columns for few blocks and of 64 (twice the workgroups per
+  // CU) for many; otherwise four blocks per wave and 64 columns
   const int nq = ldl <= 64 ? 1 : 4;
-  const int cw = nq == 1 ? (ncols > 64 ? 128 : ncols > 16 ? 64 : 16) : (ncols > 16 ? 64 : 16);
+  const int cw = nq == 1 ? (ncols > 64 && nblk < 512 ? 128 : ncols > 16 ? 64 : 16) : (ncols > 16 ? 64 : 16);
   const int nchunks = (ncols + cw - 1) / cw;
   const int64_t grid = (int64_t)nblk * nchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
