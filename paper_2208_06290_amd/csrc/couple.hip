@@ -20,7 +20,10 @@
 //   (eq. "e:node3") or the transposed solve used by the adjoint.
 // Lanes own rows of the right-hand side (2r <= 128 -> two rows per lane) and
 // the pivot value of each elimination step is broadcast with readlane.
+#include "mfma.h"
 #include "wave.h"
+
+#include <algorithm>
 
 namespace hodlr {
 
@@ -255,6 +258,105 @@ __device__ __forceinline__ void block_lu(T* K, int n2, int lane, int w, int* spi
   if (w == 0 && lane < n2) sperm[mypos] = lane;
 }
 
+// K_g (eq. "e:k") in LDS, col-major n2 x n2, from the children's reduced
+// products: item columns Rp .. Rp + r - 1 hold V_a^T Y_a (r x r)
+template <typename T>
+__device__ __forceinline__ void form_k(T* K, const T* Pa, const T* Pb, int r, int Rp, int tid) {
+  const int n2 = 2 * r;
+#pragma unroll 4
+  for (int e = tid; e < n2 * n2; e += kCfThreads) {
+    const int i = e % n2, j = e / n2;
+    const bool da = i < r && j < r, db = i >= r && j >= r;
+    const T va = Pa[min(i, r - 1) + (int64_t)(Rp + min(j, r - 1)) * r];
+    const T vb = Pb[max(i - r, 0) + (int64_t)(Rp + max(j - r, 0)) * r];
+    const T id = (i < r ? j - r == i : i - r == j) ? T(1) : T(0);
+    K[i + j * n2] = da ? va : (db ? vb : id);
+  }
+}
+
+// Gauss-Jordan elimination with partial pivoting on [K | I] for n2 <= 64,
+// n2 % 16 == 0, with the same register layout and pivot rule as block_lu
+// (lane i holds row i, wave w columns 16w .. 16w+15 of K and of the augmented
+// block).  Step j eliminates column j from every other row, including the
+// rows pivoted earlier, and scales the pivot row; afterwards the augmented
+// row of the row pivoted at step j is row j of K^{-1}, written to K (col-major).
+template <typename T>
+__device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, unsigned long long* info,
+                                         unsigned long long info_base) {
+  __shared__ T s_l[2][64];
+  __shared__ int s_pl[2][2];  // pivot lane, pivot value nonzero
+  T kc[16], ac[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int col = 16 * w + c;
+    kc[c] = (lane < n2 && col < n2) ? K[lane + col * n2] : T(0);
+    ac[c] = (lane < n2 && lane == col) ? T(1) : T(0);
+  }
+  int mypos = lane;
+  bool done = lane >= n2;
+  const int nb = n2 >> 4;
+  for (int jb = 0; jb < nb; ++jb) {
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = 16 * jb + jj;
+      const int sb = jj & 1;
+      if (w == jb) {
+        const T kj = kc[jj];
+        T v = done ? T(-1) : fabs(kj);
+        if (!done && !(v == v)) v = T(INFINITY);
+        T vmax;
+        int bk;  // pivot position (uniform)
+        wave_argmax(v, done ? 0x7fffffff : mypos, vmax, bk);
+        const unsigned long long sel = __ballot(!done && mypos == bk);
+        const int plane = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(sel));
+        const T pv = bcast(kj, plane);
+        const bool nz = pv != T(0);
+        const T rp = T(1) / pv;
+        // multipliers of the other rows; the pivot row's own entry is the scale 1 / pivot
+        s_l[sb][lane] = (lane < n2 && nz) ? (lane == plane ? rp : kj * rp) : T(0);
+        if (lane == 0) {
+          s_pl[sb][0] = plane;
+          s_pl[sb][1] = nz;
+          if (!nz) atomicMin(info, info_base | (unsigned long long)j);
+        }
+      }
+      __syncthreads();
+      const int plane = __builtin_amdgcn_readfirstlane(s_pl[sb][0]);
+      const bool nz = s_pl[sb][1] != 0;
+      const T l = s_l[sb][lane];
+      const bool me = lane == plane;
+      const int bk = __builtin_amdgcn_readfirstlane(__shfl(mypos, plane, 64));
+      if (!done && !me && mypos == j) mypos = bk;  // the row displaced by the interchange
+      if (me) {
+        done = true;
+        mypos = j;
+      }
+      if (nz) {  // uniform; a zero pivot (reported) leaves the rows as they are
+        auto elim = [&](T& x) {
+          const T p = bcast(x, plane);
+          x = me ? x * l : x - l * p;
+        };
+        // columns left of j are zero in the pivot row: nothing to do there
+        if (w == jb) {
+#pragma unroll
+          for (int c = jj + 1; c < 16; ++c) elim(kc[c]);
+        } else if (w > jb) {
+#pragma unroll
+          for (int c = 0; c < 16; ++c) elim(kc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) elim(ac[c]);
+      }
+    }
+  }
+  __syncthreads();  // every wave has read K before it is overwritten
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int col = 16 * w + c;
+    if (lane < n2 && col < n2) K[mypos + col * n2] = ac[c];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp, int Rp, const T* __restrict__ segs,
                                                                    const int32_t* __restrict__ seg_start,
@@ -278,15 +380,7 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp
   // the children's products have been reduced to one item per node
   const T* Pa = segs + (int64_t)seg_start[a] * elems;
   const T* Pb = segs + (int64_t)seg_start[b] * elems;
-#pragma unroll 4
-  for (int e = tid; e < n2 * n2; e += kCfThreads) {
-    const int i = e % n2, j = e / n2;
-    const bool da = i < r && j < r, db = i >= r && j >= r;
-    const T va = Pa[min(i, r - 1) + (int64_t)(Rp + min(j, r - 1)) * r];
-    const T vb = Pb[max(i - r, 0) + (int64_t)(Rp + max(j - r, 0)) * r];
-    const T id = (i < r ? j - r == i : i - r == j) ? T(1) : T(0);
-    K[i + j * n2] = da ? va : (db ? vb : id);
-  }
+  form_k(K, Pa, Pb, r, Rp, tid);
   __syncthreads();
   // right-hand sides of eq. "e:node1", unpermuted (the block solver applies the pivots)
   {
@@ -427,12 +521,92 @@ __global__ __launch_bounds__(kCfThreads) void couple_dinv_kernel(int n2, int kp,
   for (int i = 0; i < 16; ++i) dst[i * 16 + cc] = x[i];
 }
 
+// Coupling factor for 2r <= 64, 2r % 16 == 0: K^{-1} by block_gj, stored
+// (2r x 2r, col-major) for the solves, and W = K^{-1} rhs written directly:
+// the products run on MFMA in 64-column chunks, transposed
+// (W^T = rhs^T K^{-T}) so that lanes hold consecutive rows of W; wave w forms
+// rows 16w .. 16w+15 with its part of K^{-1} held in registers, and the
+// right-hand-side chunk is staged in LDS (where K was).
+template <typename T>
+__global__ __launch_bounds__(kCfThreads) void couple_factor_inv_kernel(int r, int Rp, const T* __restrict__ segs,
+                                                                       const int32_t* __restrict__ seg_start,
+                                                                       T* __restrict__ Kinv, T* __restrict__ W,
+                                                                       unsigned long long* info, int level, int L) {
+  using M = Mfma<T>;
+  using V = typename M::V;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* K = reinterpret_cast<T*>(smem_raw);  // n2 x n2 col-major, then the rhs chunk [c][k] (ld n2 + 1)
+  const int g = blockIdx.x;
+  const int a = 2 * g, b = 2 * g + 1;
+  const int n2 = 2 * r;
+  const int ncin = Rp + r;
+  const int64_t elems = (int64_t)r * ncin;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lq = lane >> 4;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const T* Pa = segs + (int64_t)seg_start[a] * elems;
+  const T* Pb = segs + (int64_t)seg_start[b] * elems;
+  form_k(K, Pa, Pb, r, Rp, tid);
+  __syncthreads();
+  block_gj(K, n2, lane, wid, info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16));
+  __syncthreads();
+  T* Kg = Kinv + (int64_t)g * n2 * n2;
+  for (int e = tid; e < n2 * n2; e += kCfThreads) Kg[e] = K[e];
+  // B operand: K^{-1}(16 wid + li, 4 ks + lq)
+  const bool act = 16 * wid < n2;  // uniform
+  T bk[16];
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) bk[ks] = (act && 4 * ks < n2) ? K[(16 * wid + li) + (4 * ks + lq) * n2] : T(0);
+  __syncthreads();  // K's LDS is reused for the right-hand sides
+  T* Rs = K;
+  const int ldr = n2 + 1;
+  T* Wg = W + (int64_t)g * n2 * Rp;
+  for (int c0 = 0; c0 < Rp; c0 += 64) {
+    for (int e = tid; e < 64 * n2; e += kCfThreads) {
+      const int k = e % n2, c = e / n2;
+      const int col = min(c0 + c, Rp - 1);
+      const T v = k < r ? Pa[k + (int64_t)col * r] : Pb[(k - r) + (int64_t)col * r];
+      Rs[c * ldr + k] = (c0 + c < Rp) ? v : T(0);
+    }
+    __syncthreads();
+    if (act) {
+      V acc[4];
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) acc[mb] = vzero<V>();
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+        if (4 * ks < n2) {  // uniform
+#pragma unroll
+          for (int mb = 0; mb < 4; ++mb) acc[mb] = M::mma(Rs[(16 * mb + li) * ldr + 4 * ks + lq], bk[ks], acc[mb]);
+        }
+      }
+      const int i = 16 * wid + li;
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int c = c0 + 16 * mb + M::crow(lq, t);
+          if (c < Rp) Wg[i + (int64_t)c * n2] = acc[mb][t];
+        }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 hipError_t launch_couple_factor(hipStream_t s, int nparents, int r, int kp, int Rp, const T* segs,
                                 const int32_t* d_seg_start, T* Klu, int32_t* Kpiv, int32_t* Kperm, T* Kud, T* Kinv,
                                 T* W, unsigned long long* info, int level, int L) {
   if (nparents == 0 || r == 0) return hipSuccess;
   if (kp > 128) return hipErrorInvalidValue;
+  if (couple_uses_inverse(r)) {
+    const size_t smem_inv = sizeof(T) * std::max<size_t>((size_t)4 * r * r, (size_t)64 * (2 * r + 1));
+    auto ki = couple_factor_inv_kernel<T>;
+    hipError_t e = hipFuncSetAttribute((const void*)ki, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_inv);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ki, dim3(nparents), dim3(kCfThreads), smem_inv, s, r, Rp, segs, d_seg_start, Klu, W, info,
+                       level, L);
+    return hipGetLastError();
+  }
   const size_t smem = sizeof(T) * (size_t)4 * r * r;
   auto k = couple_factor_kernel<T>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
@@ -570,10 +744,66 @@ __global__ __launch_bounds__(64) void couple_solve_reg_kernel(int r, int kp, int
   }
 }
 
+// Solves with an explicit K^{-1} (factors from couple_factor_inv_kernel):
+// one wave per parent, lane i forms row i of w = K^{-1} rhs (TRANS: K^{-T}
+// rhs), the right-hand-side columns broadcast from LDS.
+template <typename T, int TRANS>
+__global__ __launch_bounds__(64) void couple_apply_kernel(int r, int nrhs, const T* __restrict__ segs,
+                                                          const int32_t* __restrict__ seg_start,
+                                                          const T* __restrict__ Kinv, T* __restrict__ w) {
+  __shared__ T xs[kCsCols * 64];
+  const int g = blockIdx.x;
+  const int a = 2 * g, b = 2 * g + 1;
+  const int n2 = 2 * r;
+  const int lane = threadIdx.x;
+  const int64_t elems = (int64_t)r * nrhs;
+  const T* Kg = Kinv + (int64_t)g * n2 * n2;
+  T* wg = w + (int64_t)g * n2 * nrhs;
+  const bool valid = lane < n2;
+  const int ln = valid ? lane : 0;
+  const int64_t sbase = (int64_t)seg_start[ln < r ? a : b] * elems + (ln % r);
+  for (int c0 = 0; c0 < nrhs; c0 += kCsCols) {
+#pragma unroll
+    for (int c = 0; c < kCsCols; ++c) {
+      const T v = segs[sbase + (int64_t)min(c0 + c, nrhs - 1) * r];
+      xs[c * 64 + lane] = (valid && c0 + c < nrhs) ? v : T(0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    T acc[kCsCols];
+#pragma unroll
+    for (int c = 0; c < kCsCols; ++c) acc[c] = T(0);
+#pragma unroll 8
+    for (int k = 0; k < n2; ++k) {
+      const T kv = TRANS ? Kg[k + (int64_t)ln * n2] : Kg[ln + (int64_t)k * n2];
+#pragma unroll
+      for (int c = 0; c < kCsCols; ++c) acc[c] += kv * xs[c * 64 + k];
+    }
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < kCsCols; ++c)
+        if (c0 + c < nrhs) wg[lane + (int64_t)(c0 + c) * n2] = acc[c];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 template <typename T>
 hipError_t launch_couple_solve(hipStream_t s, int trans, int nparents, int r, int kp, int nrhs, const T* segs,
                                const int32_t* d_seg_start, const T* Klu, const int32_t* Kperm, const T* Kud, T* w) {
   if (nparents == 0 || r == 0 || nrhs == 0) return hipSuccess;
+  if (couple_uses_inverse(r)) {
+    if (trans)
+      hipLaunchKernelGGL((couple_apply_kernel<T, 1>), dim3(nparents), dim3(64), 0, s, r, nrhs, segs, d_seg_start,
+                         Klu, w);
+    else
+      hipLaunchKernelGGL((couple_apply_kernel<T, 0>), dim3(nparents), dim3(64), 0, s, r, nrhs, segs, d_seg_start,
+                         Klu, w);
+    return hipGetLastError();
+  }
   if (2 * r <= 64) {
     if (trans)
       hipLaunchKernelGGL((couple_solve_reg_kernel<T, 1>), dim3(nparents), dim3(64), 0, s, r, kp, nrhs, segs,

@@ -469,7 +469,7 @@ hodlr_status run_factor(hodlr_factors* F, hipStream_t st) {
                                                    tp<T>(F->Klu) + F->koff[p], F->Kpiv + F->kvoff[p],
                                                    F->Kperm + F->kvoff[p], tp<T>(F->Kud) + F->kvoff[p],
                                                    tp<T>(F->Kinv) + F->kioff[p], tp<T>(F->W), F->d_info + 1, p, L)));
-      if (Rp > 0 && r > 0)
+      if (Rp > 0 && r > 0 && !couple_uses_inverse(r))
         HL("couple_trsm", (launch_block_trsm<T>(st, 0, 1 << p, kp, 2 * r, (int64_t)2 * r * Rp,
                                                 tp<T>(F->Klu) + F->koff[p], F->Kperm + F->kvoff[p],
                                                 tp<T>(F->Kinv) + F->kioff[p], tp<T>(F->W), 2 * r, Rp)));

@@ -105,8 +105,16 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int t
 template <typename T>
 hipError_t launch_segment_reduce(hipStream_t s, int nsegs, const int2* d_desc, int64_t elems, const T* P, T* out);
 
+// Coupling systems with 2r <= 64 and 2r % 16 == 0 are inverted explicitly
+// (Gauss-Jordan with partial pivoting): the factor stores K^{-1} (2r x 2r,
+// col-major) in place of the LU, W receives K^{-1} rhs directly and the solves
+// apply K^{-1} or its transpose.  Other ranks keep the LU, its 16 x 16 diagonal
+// inverses and the block solver.
+__host__ __device__ inline bool couple_uses_inverse(int r) { return r > 0 && 2 * r <= 64 && (2 * r) % 16 == 0; }
+
 // Coupling factor for all parents of one level (children have rank r, W has Rp columns);
-// K factors stored kp x kp (kp = 2r rounded up to 16), W gets the unsolved right-hand sides.
+// K factors stored kp x kp (kp = 2r rounded up to 16); W gets the unsolved right-hand
+// sides (LU) or the solved ones (explicit inverse).
 // Segments of child node c: [seg_start[c], seg_start[c+1]), each r x (Rp + r) col-major.
 template <typename T>
 hipError_t launch_couple_factor(hipStream_t s, int nparents, int r, int kp, int Rp, const T* segs,
