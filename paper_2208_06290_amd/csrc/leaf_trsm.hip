@@ -8,16 +8,19 @@
 // of the solution stage (Alg. "a:gpus"), and for the coupling solves with the
 // LU of K (eqs. "e:node1", "e:node3").
 //
-// One workgroup (256 threads = 4 waves) per (block, 64-column chunk).  The
-// chunk (<= 256 rows) stays in MFMA accumulators for the whole solve: wave w
-// owns the 16-row blocks b with b % 4 == w.  The inverses of the 16 x 16
-// diagonal blocks of L and U come with the factorization and are staged in
-// LDS per sweep, so every block step is a contraction: the owning wave forms
-// X_k = inv(M_kk) B_k, publishes X_k through LDS (double buffered, one
-// barrier per step), and every wave applies B_b -= M_bk X_k to its blocks on
-// MFMA with operands fetched before the barrier.  The products run
-// transposed (X^T = B^T M^{-T}) so that accumulator rows are matrix rows on
-// the lanes: every global load and store covers whole 128-byte lines.
+// One workgroup per (block, chunk of columns).  The chunk (<= 256 rows)
+// stays in MFMA accumulators for the whole solve: wave w of NW owns the
+// 16-row blocks b with b % NW == w.  The inverses of the 16 x 16 diagonal
+// blocks of L and U come with the factorization, so every block step is a
+// contraction: the owning wave forms X_k = inv(M_kk) B_k, publishes X_k
+// through LDS (double buffered, one barrier per step), and every wave applies
+// B_b -= M_bk X_k to its blocks on MFMA; the factor operands and the next
+// owner's inverted diagonal block are fetched before the barrier.  The
+// products run transposed (X^T = B^T M^{-T}) so that accumulator rows are
+// matrix rows on the lanes: every global load and store covers whole
+// 128-byte lines.  Leaf blocks take 32-column chunks with 128 registers per
+// lane (four workgroups per CU: the steps are short and latency-bound, so
+// more resident workgroups pay more than wider chunks).
 #include "mfma.h"
 
 namespace hodlr {
@@ -25,7 +28,7 @@ namespace hodlr {
 constexpr int kTwLd = 17;  // padded row length of the owner's 16 x 16 turn-around buffer
 
 template <typename T, typename S, int TRANS, int NW, int NQ, int NCB>
-__global__ __launch_bounds__(64 * NW, 8 / NW) void trsm_kernel(int ldl, const int64_t* __restrict__ leaf_off,
+__global__ __launch_bounds__(64 * NW, NW == 4 ? (NCB <= 2 ? 4 : 2) : (NCB <= 2 ? 2 : 1)) void trsm_kernel(int ldl, const int64_t* __restrict__ leaf_off,
                                                              int64_t ostride, int mfix, const T* __restrict__ lu,
                                                              const int32_t* __restrict__ perm,
                                                              const T* __restrict__ dinv, const S* B, int64_t ldb,
@@ -35,7 +38,6 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void trsm_kernel(int ldl, const in
   using V = typename M::V;
   constexpr int kThreads = 64 * NW;
   constexpr int kBlocks = NW * NQ;  // 16-row blocks of a block (row block b is owned by wave b % NW)
-  __shared__ T invA[kBlocks * 256];  // inverse diagonal blocks of the current sweep, [kb][i][j]
   constexpr int kCwT = 16 * NCB;     // columns of a chunk
   __shared__ T xk[2][16 * kCwT];   // published block X_k: [row][col]
   __shared__ T tw[NW][16 * kTwLd];  // per-wave turn-around of the owner's block
@@ -66,17 +68,18 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void trsm_kernel(int ldl, const in
   const T* DI = dinv + (int64_t)a * 2 * nbd * 256;  // [0][kb]: inv(L_kk), [1][kb]: inv(U_kk)
   T* twv = tw[w];
 
-  // stage inv(M_kk) of a sweep: sweep 0 is L (trans 0) or U^T (trans 1), sweep 1 is U or L^T
-  auto stage_inv = [&](int sweep) {
+  // B operand of X_k^T = B_k^T inv(M_kk)^T: inv(M_kk)(li, 4 ks + lq) for ks = 0..3,
+  // read from the factorization's inverted diagonal blocks (sweep 0 is L
+  // (trans 0) or U^T (trans 1), sweep 1 is U or L^T)
+  auto load_inv = [&](int sweep, int k, T (&iv)[4]) {
     const int which = TRANS ? 1 - sweep : sweep;
-    const T* src = DI + (int64_t)which * nbd * 256;
-    for (int e = tid; e < nbk * 256; e += kThreads) {
-      const int kb = e >> 8, i = (e >> 4) & 15, j = e & 15;
-      invA[e] = TRANS ? src[kb * 256 + j * 16 + i] : src[e];
+    const T* src = DI + ((int64_t)which * nbd + k) * 256;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int j = 4 * ks + lq;
+      iv[ks] = TRANS ? src[j * 16 + li] : src[li * 16 + j];
     }
   };
-
-  stage_inv(0);
 
   // The chunk is held transposed: accumulator block (q, cb), register t holds
   // X(16 (NW q + w) + li, c0 + 16 cb + crow(lq, t)), so the 16 lanes of a row
@@ -96,20 +99,19 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void trsm_kernel(int ldl, const in
         acc[q][cb][t] = (row < m && col < ncols) ? v : T(0);
       }
   }
-  __syncthreads();  // invA staged; B may alias X: all loads of the chunk precede any store
+  __syncthreads();  // B may alias X: all loads of the chunk precede any store
 
   // X_k^T = B_k^T inv(M_kk)^T for the wave owning block k (accumulator block
   // q): the block turns around through LDS to become the A operand; the
   // result stays in the accumulators and is published as X_k[row][col]
-  auto owner = [&](int q, int k, T* xb) {
+  auto owner = [&](int q, const T (&iv)[4], T* xb) {
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) twv[li * kTwLd + M::crow(lq, t)] = acc[q][cb][t];
       V nv = vzero<V>();
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
-        nv = M::mma(twv[(4 * ks + lq) * kTwLd + li], invA[k * 256 + li * 16 + 4 * ks + lq], nv);
+      for (int ks = 0; ks < 4; ++ks) nv = M::mma(twv[(4 * ks + lq) * kTwLd + li], iv[ks], nv);
       acc[q][cb] = nv;
 #pragma unroll
       for (int t = 0; t < 4; ++t) xb[li * kCwT + 16 * cb + M::crow(lq, t)] = nv[t];
@@ -128,11 +130,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void trsm_kernel(int ldl, const in
   // constant; steps past the last block of a short leaf are skipped (uniform).
 #pragma clang loop unroll(full)
   for (int sweep = 0; sweep < 2; ++sweep) {
-    if (sweep == 1) {
-      __syncthreads();
-      stage_inv(1);
-      __syncthreads();
-    }
+
 #pragma clang loop unroll(full)
     for (int st = 0; st < kBlocks; ++st) {
       const int k = sweep == 0 ? st : kBlocks - 1 - st;
@@ -143,7 +141,11 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void trsm_kernel(int ldl, const in
         T* xb = xk[sidx & 1];
         T* xn = xk[(sidx + 1) & 1];
         // the first step's X_k is formed here, later ones one step ahead (look-ahead)
-        if (sidx == 0 && w == wk) owner(q, k, xb);
+        if (sidx == 0 && w == wk) {
+          T iv0[4];
+          load_inv(sweep, k, iv0);
+          owner(q, iv0, xb);
+        }
         // the factor operands M(16 b + li, 16 k + 4 ks + lq) of this wave's blocks
         // on the far side of k do not depend on X_k: fetched before the barrier
         // (clamped in range, no branches)
@@ -158,16 +160,18 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void trsm_kernel(int ldl, const in
             av[q2][ks] = -(TRANS ? F[j + (int64_t)i * ldl] : F[i + (int64_t)j * ldl]);
           }
         }
-        __syncthreads();
         // look-ahead: the wave owning the next block updates it first and forms
         // X_next at once, so the next step starts without waiting for it
         const int kn = sweep == 0 ? k + 1 : k - 1;
         const bool nxt = sweep == 0 ? kn < nbk : kn >= 0;
         const int qn = kn / NW, wn = kn % NW;
         const bool la = nxt && w == wn;  // uniform
+        T ivn[4];
+        if (la) load_inv(sweep, kn, ivn);  // fetched before the barrier too
+        __syncthreads();
         if (la) {
           update(qn, av, xb);
-          owner(qn, kn, xn);
+          owner(qn, ivn, xn);
         }
 #pragma unroll
         for (int q2 = 0; q2 < NQ; ++q2) {
@@ -206,9 +210,9 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
   if (ldl % 16 || ldl > 256) return hipErrorInvalidValue;
   // blocks of at most 64 rows (coupling systems): one 16-row block per wave,
   // chunks of 128 columns for few blocks and of 64 (twice the workgroups per
-  // CU) for many; otherwise four blocks per wave and 64 columns
+  // CU) for many; otherwise four blocks per wave and 32 columns
   const int nq = ldl <= 64 ? 1 : 4;
-  const int cw = nq == 1 ? (ncols > 64 && nblk < 512 ? 128 : ncols > 16 ? 64 : 16) : (ncols > 16 ? 64 : 16);
+  const int cw = nq == 1 ? (ncols > 64 && nblk < 512 ? 128 : ncols > 16 ? 64 : 16) : (ncols > 16 ? 32 : 16);
   const int nchunks = (ncols + cw - 1) / cw;
   const int64_t grid = (int64_t)nblk * nchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
@@ -223,7 +227,7 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
     else if (cw == 64) HODLR_TS(TR, 4, 1, 4);  \
     else HODLR_TS(TR, 4, 1, 1);                \
   } else {                                     \
-    if (cw == 64) HODLR_TS(TR, 4, 4, 4);       \
+    if (cw == 32) HODLR_TS(TR, 4, 4, 2);       \
     else HODLR_TS(TR, 8, 2, 1);                \
   }
   if (trans) {
