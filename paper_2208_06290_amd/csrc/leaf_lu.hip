@@ -15,7 +15,11 @@
 //      tracks its position; each wave publishes its best candidate's row in
 //      LDS and every thread selects the winner, one barrier per column.
 // Entries are stored by original row while factoring (later interchanges move
-// no data); a final pass writes them in pivoted order.
+// no data); a final pass writes them in pivoted order.  Four workgroups per CU
+// (the panel steps are latency-bound): at most 128 registers per lane and
+// 40 KB of LDS, so the panel rows reach the registers 8 columns at a time
+// and the diagonal-block inverses are formed with rolled loops, their
+// columns in LDS.
 //
 // Output per leaf a (block of ldl x ldl, column-major, ld = ldl; ldl = m_max
 // rounded up to 16):
@@ -35,14 +39,17 @@ constexpr int kLuThreads = 256;
 constexpr int kCW = 32;  // chunk (panel) width
 
 template <typename T, typename S, int CW>
-__global__ __launch_bounds__(kLuThreads, CW == 16 ? 3 : 2) void leaf_lu_kernel(int ldl, const int64_t* __restrict__ leaf_off,
+__global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const int64_t* __restrict__ leaf_off,
                                                              const S* __restrict__ D, int64_t ldd, T* lu,
                                                              int32_t* __restrict__ piv, int32_t* __restrict__ perm,
                                                              T* __restrict__ udinv, T* invl,
                                                              unsigned long long* info) {
   using M = Mfma<T>;
   using V = typename M::V;
-  __shared__ T stage[256 * CW];  // panel rows, row-major [row][32]
+  // staging area: the earlier chunks' diagonal-block inverses for the sweep
+  // (<= 14 blocks of 256), the panel rows 8 columns at a time ([row][8]), the
+  // new diagonal block and the inversion scratch (2 x 1024)
+  __shared__ T stage[14 * 256];
   __shared__ T xk[2][16 * CW];   // published X_k [row][col]
   __shared__ T crow_[2][4][CW];  // per wave: the row of its best pivot candidate
   __shared__ T cval[2][4];        // per wave: |candidate|
@@ -137,7 +144,7 @@ __global__ __launch_bounds__(kLuThreads, CW == 16 ? 3 : 2) void leaf_lu_kernel(i
         }
       }
     }
-    // U rows above the panel are final; panel rows go to LDS
+    // U rows above the panel are final
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -146,24 +153,30 @@ __global__ __launch_bounds__(kLuThreads, CW == 16 ? 3 : 2) void leaf_lu_kernel(i
         for (int t = 0; t < 4; ++t) {
           const int row = 16 * (4 * q + w) + M::crow(lq, t);
           const int col = 16 * cb + li;
-          if (row < m) {
-            if (row < c0) {
-              if (col < cw) F[pm[row] + (int64_t)(c0 + col) * ldl] = acc[q][cb][t];
-            } else {
-              stage[(row - c0) * CW + col] = acc[q][cb][t];
-            }
-          }
+          if (row < m && row < c0 && col < cw) F[pm[row] + (int64_t)(c0 + col) * ldl] = acc[q][cb][t];
         }
-    __syncthreads();
     // 3. panel factorization, one thread per panel row
     const int pr = m - c0;
     const bool own = tid < pr;
     int mypos = tid;
     bool done = false;
     const int orig = own ? pm[c0 + tid] : 0;
+    // panel rows to the registers through LDS, 8 columns at a time
     T r[CW];
 #pragma unroll
-    for (int cc = 0; cc < CW; ++cc) r[cc] = own ? stage[tid * CW + cc] : T(0);
+    for (int h = 0; h < CW / 8; ++h) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int row = 16 * (4 * q + w) + M::crow(lq, t);
+          if (row < m && row >= c0 && (li >> 3) == (h & 1)) stage[(row - c0) * 8 + (li & 7)] = acc[q][h >> 1][t];
+        }
+      __syncthreads();
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) r[8 * h + cc] = own ? stage[tid * 8 + cc] : T(0);
+      __syncthreads();
+    }
 #pragma unroll
     for (int j = 0; j < CW; ++j) {
       if (j < cw) {
@@ -240,30 +253,34 @@ __global__ __launch_bounds__(kLuThreads, CW == 16 ? 3 : 2) void leaf_lu_kernel(i
       const int kb = (CW / 16) * c + half;
       const int g0 = 16 * kb;
       const T* Bk = dblk + (16 * half) * CW + 16 * half;  // element (i, j) at Bk[i * CW + j]
+      T* xs = stage + CW * CW + tid * 16;                  // this thread's column, in LDS (rolled loops: few registers)
       if (half < CW / 16 && kb < nbk) {
-        T x[16];
         if (tid < 32) {
-#pragma unroll
+#pragma unroll 1
           for (int i = 0; i < 16; ++i) {
             T sacc = (i == cc) ? T(1) : T(0);
-#pragma unroll
-            for (int jj = 0; jj < i; ++jj) sacc -= ((g0 + i < m) ? Bk[i * CW + jj] : T(0)) * x[jj];
-            x[i] = (i >= cc) ? sacc : T(0);
+            for (int jj = 0; jj < i; ++jj) {
+              const T bv = Bk[i * CW + jj];
+              sacc -= ((g0 + i < m) ? bv : T(0)) * xs[jj];
+            }
+            xs[i] = (i >= cc) ? sacc : T(0);
           }
 #pragma unroll
-          for (int i = 0; i < 16; ++i) IL[kb * 256 + i * 16 + cc] = x[i];
+          for (int i = 0; i < 16; ++i) IL[kb * 256 + i * 16 + cc] = xs[i];
         } else {
-#pragma unroll
+#pragma unroll 1
           for (int i = 15; i >= 0; --i) {
             T sacc = (i == cc) ? T(1) : T(0);
-#pragma unroll
-            for (int jj = i + 1; jj < 16; ++jj)
-              sacc -= ((g0 + i < m && g0 + jj < m) ? Bk[i * CW + jj] : T(0)) * x[jj];
-            const T d = (g0 + i < m) ? Bk[i * CW + i] : T(1);
-            x[i] = (i <= cc) ? sacc / d : T(0);
+            for (int jj = i + 1; jj < 16; ++jj) {
+              const T bv = Bk[i * CW + jj];
+              sacc -= ((g0 + i < m && g0 + jj < m) ? bv : T(0)) * xs[jj];
+            }
+            const T dv = Bk[i * CW + i];
+            const T d = (g0 + i < m) ? dv : T(1);
+            xs[i] = (i <= cc) ? sacc / d : T(0);
           }
 #pragma unroll
-          for (int i = 0; i < 16; ++i) IL[(ldl / 16 + kb) * 256 + i * 16 + cc] = x[i];
+          for (int i = 0; i < 16; ++i) IL[(ldl / 16 + kb) * 256 + i * 16 + cc] = xs[i];
         }
       }
     } else if (tid < 64 + CW && c0 + tid - 64 < ldl) {
