@@ -159,7 +159,7 @@ struct hodlr_factors {
   std::vector<Tile*> d_tiles;                 // per tile level q = 0..L
   std::vector<int> ntiles;                    // per q
   std::vector<std::vector<Tile>> h_tiles;     // per q (host copy)
-  std::vector<int> tiles_aligned;             // per q: every tile height is a multiple of 16
+  std::vector<int> tiles_aligned;             // per q: bit 0 every tile height % 16 == 0, bit 1 % 32 == 0
   int64_t ldy = 0, gsy = 256;                 // Y layout: row i, column c at (i >> 8) * gsy + (i & 255) + c * ldy
   std::vector<std::vector<int>> tile_start;   // per q, 2^q + 1
   std::map<std::pair<int, int>, ProdPlan> prods;
@@ -312,9 +312,10 @@ hodlr_status plan(hodlr_factors* F) {
     build_tiles(F, q, tl, F->tile_start[q]);
     F->ntiles[q] = (int)tl.size();
     F->h_tiles[q] = tl;
-    F->tiles_aligned[q] = 1;
+    F->tiles_aligned[q] = 3;
     for (const Tile& t : tl)
       if (t.nrows % 16) F->tiles_aligned[q] = 0;
+      else if (t.nrows % 32) F->tiles_aligned[q] &= 1;
     hodlr_status s = F->mem.alloc(&F->d_tiles[q], tl.size());
     if (s) return s;
     if (hipMemcpy(F->d_tiles[q], tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess)

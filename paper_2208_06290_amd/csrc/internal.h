@@ -84,7 +84,8 @@ hipError_t launch_block_trsm(hipStream_t s, int trans, int nblk, int ldl, int m,
 //   product: P_tile(0:kb, 0:nz) = B1(tile, 0:kb)^T * Z(tile, 0:nz)      (if kb > 0)
 // nd = tile.node >> node_shift; W for node nd starts at W + (nd >> 1) * w_pstride + (nd & 1) * ka, ld = w_ld.
 // P_tile starts at P + tile * kb * nz, col-major ld = kb.
-// tiles_aligned: every tile height is a multiple of 16 (enables the fast kernel).
+// tiles_aligned: bit 0 - every tile height is a multiple of 16 (enables the fast kernel);
+// bit 1 - a multiple of 32 (4-byte Z: two rows per lane).
 // Row addressing of the Z, A1 and B1 operands: row i of an operand lives at
 // (i >> 8) * gs + (i & 255) (plus column * ld).  gs = 256 is the plain
 // column-major layout; gs = 256 * ncols with ld = 256 is the row-group blocked

@@ -175,10 +175,14 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
 // loaded coalesced and turned around the same way.  A chunk is 16 NCB
 // columns of Z (NCB = 1 for narrow right-hand sides, else 4).  Columns past
 // nz are computed on zeros and never stored; their loads are redirected to an
-// in-range column, so no access leaves the operands.
+// in-range column, so no access leaves the operands.  RP = 2 (4-byte Z, tile
+// heights multiples of 32): each lane holds two consecutive rows, loaded and
+// stored as one 8-byte access, so 16 lanes still cover a whole 128-byte line;
+// the even and the odd rows form two 16-row MFMA blocks (the product's sum
+// over rows does not depend on their order).
 constexpr int kZtLd = 17;  // padded row length of the per-wave 16 x 16 turn-around buffer
 
-template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE>
+template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE, int RP>
 __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level_pass_fast_kernel(
     const Tile* __restrict__ tiles, int zchunks, int c_base, int bchunks, TZ* Z, int64_t ldz, int nz, const SA* __restrict__ A1,
     int64_t lda, const TZ* __restrict__ W, int64_t w_ld, int64_t w_pstride, int node_shift,
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
   const int c0 = c_base + zchunk * kCw;
   const int ncz = MODE == 0 ? kCw : min(kCw, nz - c0);  // valid columns of this chunk
   const int wr0 = 64 * w;
-  const int nrb = max(0, min(4, (nrows - wr0) >> 4));  // 16-row blocks of this wave
+  const int nrb = max(0, min(4 / RP, (nrows - wr0) >> (RP == 2 ? 5 : 4)));  // 16 RP-row blocks of this wave
   const int kc0 = bchunk * 64;
   TZ* zt = Ws + kCw * ka + w * kWave;
   TZ* bt = zt + 16 * kZtLd;
@@ -224,14 +228,16 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
   const auto zr = buf_rsrc(Z + group_row(tl.row0, gs.z) + wr0 + (int64_t)c0 * ldz);
   const auto ar = buf_rsrc(NKS > 0 ? A1 + group_row(tl.row0, gs.a) + wr0 : A1);  // A1 / B1 are null when unused
   const auto br = buf_rsrc(prod ? B1 + group_row(tl.row0, gs.b) + wr0 + (int64_t)kc0 * ldb : B1);
-  const uint32_t zrow = (uint32_t)li * (uint32_t)sizeof(TZ);
+  const uint32_t zrow = (uint32_t)(RP * li) * (uint32_t)sizeof(TZ);
   const uint32_t zl = zrow + (uint32_t)((int64_t)M::crow_l(lq) * ldz) * (uint32_t)sizeof(TZ);
-  const uint32_t al = (uint32_t)(li + (int64_t)lq * lda) * (uint32_t)sizeof(SA);
-  const uint32_t bl = (uint32_t)(li + (int64_t)lq * ldb) * (uint32_t)sizeof(SB);
+  const uint32_t al = (uint32_t)(RP * li + (int64_t)lq * lda) * (uint32_t)sizeof(SA);
+  const uint32_t bl = (uint32_t)(RP * li + (int64_t)lq * ldb) * (uint32_t)sizeof(SB);
+  constexpr uint32_t kRbRows = 16 * RP;  // rows of one row block
   // Z(16 rb + li, c0 + 16 cb + crow(lq, t)) is register t of the Z^T accumulator
-  // block cb.  The lane-uniform column part is clamped into the chunk; a lane
-  // whose own column is past nz drops its lane part and reads the clamped
-  // column instead (its value is replaced by zero).
+  // block cb (RP = 2: rows 32 rb + 2 li + h of block h).  The lane-uniform
+  // column part is clamped into the chunk; a lane whose own column is past nz
+  // drops its lane part and reads the clamped column instead (its value is
+  // replaced by zero).
   // MODE 0: every column of the chunk is valid; MODE 1: the valid columns
   // are whole 16-column blocks (later blocks re-read the last valid one, a
   // lane-uniform clamp); MODE 2: any count (per-lane test)
@@ -247,34 +253,47 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
     return (uint32_t)((int64_t)col * ldz * (int64_t)sizeof(TZ));
   };
   auto zvo = [&](int rb, int cb, int t) -> uint32_t {
-    return (MODE < 2 || zok(cb, t) ? zl : zrow) + 16u * (uint32_t)rb * (uint32_t)sizeof(TZ);
+    return (MODE < 2 || zok(cb, t) ? zl : zrow) + kRbRows * (uint32_t)rb * (uint32_t)sizeof(TZ);
   };
-  auto load_z = [&](int rb, V (&dst)[NCB]) {
+  auto load_z = [&](int rb, V (&d0)[NCB], V (&d1)[NCB]) {
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const TZ v = Buf<TZ>::load(zr, zvo(rb, cb, t), zso(cb, t));
-        dst[cb][t] = zok(cb, t) ? v : TZ(0);
+        TZ v0, v1 = TZ(0);
+        if (RP == 2) Buf2<TZ>::load(zr, zvo(rb, cb, t), zso(cb, t), v0, v1);
+        else v0 = Buf<TZ>::load(zr, zvo(rb, cb, t), zso(cb, t));
+        d0[cb][t] = zok(cb, t) ? v0 : TZ(0);
+        d1[cb][t] = zok(cb, t) ? v1 : TZ(0);
       }
   };
-  // B operand of the update: -A1(16 rb + li, 4 ks + lq)
-  auto load_a = [&](int rb, TZ (&dst)[NKS > 0 ? NKS : 1]) {
+  // B operand of the update: -A1(row, 4 ks + lq) for the lane's row(s)
+  auto load_a = [&](int rb, TZ (&d0)[NKS > 0 ? NKS : 1], TZ (&d1)[NKS > 0 ? NKS : 1]) {
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks)
-      dst[ks] = -(TZ)Buf<SA>::load(ar, al + 16u * (uint32_t)rb * (uint32_t)sizeof(SA),
-                                   (uint32_t)((int64_t)(4 * ks) * lda * (int64_t)sizeof(SA)));
+    for (int ks = 0; ks < NKS; ++ks) {
+      const uint32_t vo = al + kRbRows * (uint32_t)rb * (uint32_t)sizeof(SA);
+      const uint32_t so = (uint32_t)((int64_t)(4 * ks) * lda * (int64_t)sizeof(SA));
+      SA x0, x1 = SA(0);
+      if (RP == 2) Buf2<SA>::load(ar, vo, so, x0, x1);
+      else x0 = Buf<SA>::load(ar, vo, so);
+      d0[ks] = -(TZ)x0;
+      d1[ks] = -(TZ)x1;
+    }
   };
-  // B1(16 rb + li, kc0 + 4 i + lq); the last B1 chunk may hold fewer than kb
+  // B1(row, kc0 + 4 i + lq); the last B1 chunk may hold fewer than kb
   // columns (a multiple of 16): the others read column kc0 and are zeroed
   const int kbc = prod ? min(kb, kb_total - kc0) : 0;
-  auto load_b = [&](int rb, TZ (&dst)[MB > 0 ? 4 * MB : 1]) {
+  auto load_b = [&](int rb, TZ (&d0)[MB > 0 ? 4 * MB : 1], TZ (&d1)[MB > 0 ? 4 * MB : 1]) {
 #pragma unroll
     for (int i = 0; i < 4 * MB; ++i) {
       const bool ok = 4 * i < kbc;  // uniform
-      const TZ v = (TZ)Buf<SB>::load(br, bl + 16u * (uint32_t)rb * (uint32_t)sizeof(SB),
-                                     (uint32_t)((int64_t)(ok ? 4 * i : 0) * ldb * (int64_t)sizeof(SB)));
-      dst[i] = ok ? v : TZ(0);
+      const uint32_t vo = bl + kRbRows * (uint32_t)rb * (uint32_t)sizeof(SB);
+      const uint32_t so = (uint32_t)((int64_t)(ok ? 4 * i : 0) * ldb * (int64_t)sizeof(SB));
+      SB x0, x1 = SB(0);
+      if (RP == 2) Buf2<SB>::load(br, vo, so, x0, x1);
+      else x0 = Buf<SB>::load(br, vo, so);
+      d0[i] = ok ? (TZ)x0 : TZ(0);
+      d1[i] = ok ? (TZ)x1 : TZ(0);
     }
   };
 
@@ -284,45 +303,69 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) pacc[mb][cb] = vzero<V>();
 
+  // update of one 16-row MFMA block, and its contribution to the product
+  auto update = [&](V (&acc)[NCB], const TZ (&acur)[NKS > 0 ? NKS : 1]) {
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        acc[cb] = M::mma(Ws[(4 * ks + lq) * kCw + 16 * cb + li], acur[ks], acc[cb]);
+  };
+  auto stage_b = [&](const TZ (&bcur)[MB > 0 ? 4 * MB : 1]) {
+#pragma unroll
+    for (int i = 0; i < 4 * MB; ++i) bt[li * kBtLd + 4 * i + lq] = bcur[i];
+  };
+  auto product = [&](const V (&acc)[NCB]) {
+    // P(j, c) += sum_r B1(r, j) Z(r, c); K-step kk takes rows 4 kk + lq; the
+    // turned-around B1 block is read into registers once
+    TZ bv[4][MB > 0 ? MB : 1];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) bv[kk][mb] = bt[(4 * kk + lq) * kBtLd + 16 * mb + li];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) zt[li * kZtLd + M::crow(lq, t)] = acc[cb][t];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const TZ zv = zt[(4 * kk + lq) * kZtLd + li];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) pacc[mb][cb] = M::mma(bv[kk][mb], zv, pacc[mb][cb]);
+      }
+    }
+  };
+
   if (NKS > 0) __syncthreads();  // W chunk staged
   // no software prefetch: latency is hidden by the other resident waves
 #pragma unroll 1
   for (int rb = 0; rb < nrb; ++rb) {
-    V acc[NCB];
-    TZ acur[NKS > 0 ? NKS : 1];
-    TZ bcur[MB > 0 ? 4 * MB : 1];
-    load_z(rb, acc);
-    if (NKS > 0) load_a(rb, acur);
+    V acc0[NCB], acc1[NCB];
+    TZ a0[NKS > 0 ? NKS : 1], a1[NKS > 0 ? NKS : 1];
+    TZ b0[MB > 0 ? 4 * MB : 1], b1[MB > 0 ? 4 * MB : 1];
+    load_z(rb, acc0, acc1);
+    if (NKS > 0) load_a(rb, a0, a1);
     if (prod) {
-      load_b(rb, bcur);
-#pragma unroll
-      for (int i = 0; i < 4 * MB; ++i) bt[li * kBtLd + 4 * i + lq] = bcur[i];
+      load_b(rb, b0, b1);
+      stage_b(b0);
     }
     if (NKS > 0) {
-#pragma unroll
-      for (int ks = 0; ks < NKS; ++ks)
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          acc[cb] = M::mma(Ws[(4 * ks + lq) * kCw + 16 * cb + li], acur[ks], acc[cb]);
+      update(acc0, a0);
+      if (RP == 2) update(acc1, a1);
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-          if (zok(cb, t)) Buf<TZ>::store(acc[cb][t], zr, zvo(rb, cb, t), zso(cb, t));
+          if (zok(cb, t)) {
+            if (RP == 2) Buf2<TZ>::store(acc0[cb][t], acc1[cb][t], zr, zvo(rb, cb, t), zso(cb, t));
+            else Buf<TZ>::store(acc0[cb][t], zr, zvo(rb, cb, t), zso(cb, t));
+          }
     }
     if (prod) {
-      // P(j, c) += sum_r B1(r, j) Z(r, c); K-step kk takes rows 4 kk + lq
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) zt[li * kZtLd + M::crow(lq, t)] = acc[cb][t];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const TZ zv = zt[(4 * kk + lq) * kZtLd + li];
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-            pacc[mb][cb] = M::mma(bt[(4 * kk + lq) * kBtLd + 16 * mb + li], zv, pacc[mb][cb]);
-        }
+      product(acc0);
+      if (RP == 2) {
+        stage_b(b1);  // after the even block's reads of bt (in order within the wave)
+        product(acc1);
       }
     }
   }
@@ -362,7 +405,7 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
   }
 }
 
-template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE>
+template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE, int RP>
 static hipError_t launch_part(hipStream_t s, int ntiles, int zchunks, int c_base, int nz, int bchunks,
                               const Tile* tiles, TZ* Z, int64_t ldz, const SA* A1, int64_t lda, const TZ* W,
                               int64_t w_ld, int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
@@ -374,7 +417,7 @@ static hipError_t launch_part(hipStream_t s, int ntiles, int zchunks, int c_base
   const size_t smem = smem_main > smem_red ? smem_main : smem_red;
   const int64_t grid = (int64_t)ntiles * zchunks * bchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  auto k = level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, MODE>;
+  auto k = level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, MODE, RP>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kLpThreads), smem, s, tiles, zchunks, c_base, bchunks, Z, ldz, nz,
@@ -385,34 +428,34 @@ static hipError_t launch_part(hipStream_t s, int ntiles, int zchunks, int c_base
 // Columns of Z in up to three launches: chunks of 64, then the whole 16-column
 // blocks that are left as one narrower chunk, then a last partial block
 // (per-lane column test).  Every launch computes only columns that exist.
-template <typename TZ, typename SA, typename SB, int MB, int NKS>
+template <typename TZ, typename SA, typename SB, int MB, int NKS, int RP>
 static hipError_t launch_fast(hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z, int64_t ldz,
                               const SA* A1, int64_t lda, const TZ* W, int64_t w_ld, int64_t w_pstride,
                               int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P, GroupStrides gs) {
   const int n64 = nz / 64, nb = (nz % 64) / 16, tail = nz % 16;
-  hipError_t e = launch_part<TZ, SA, SB, MB, NKS, 4, 0>(s, ntiles, n64, 0, nz, bchunks, tiles, Z, ldz, A1, lda, W,
+  hipError_t e = launch_part<TZ, SA, SB, MB, NKS, 4, 0, RP>(s, ntiles, n64, 0, nz, bchunks, tiles, Z, ldz, A1, lda, W,
                                                          w_ld, w_pstride, node_shift, B1, ldb, kb, P, gs);
   if (e != hipSuccess) return e;
   const int cb = 64 * n64;
 #define HODLR_LPB(NCBV)                                                                                          \
-  e = launch_part<TZ, SA, SB, MB, NKS, NCBV, 0>(s, ntiles, 1, cb, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,  \
+  e = launch_part<TZ, SA, SB, MB, NKS, NCBV, 0, RP>(s, ntiles, 1, cb, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,  \
                                                  w_pstride, node_shift, B1, ldb, kb, P, gs)
   if (nb == 1) HODLR_LPB(1);
   else if (nb == 2) HODLR_LPB(2);
   else if (nb == 3) HODLR_LPB(3);
 #undef HODLR_LPB
   if (e != hipSuccess) return e;
-  return launch_part<TZ, SA, SB, MB, NKS, 1, 2>(s, ntiles, tail ? 1 : 0, cb + 16 * nb, nz, bchunks, tiles, Z, ldz, A1,
+  return launch_part<TZ, SA, SB, MB, NKS, 1, 2, RP>(s, ntiles, tail ? 1 : 0, cb + 16 * nb, nz, bchunks, tiles, Z, ldz, A1,
                                                 lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P, gs);
 }
 
-template <typename TZ, typename SA, typename SB, int MB>
+template <typename TZ, typename SA, typename SB, int MB, int RP>
 static hipError_t launch_fast_nks(int nks, hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z,
                                   int64_t ldz, const SA* A1, int64_t lda, const TZ* W, int64_t w_ld,
                                   int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
                                   GroupStrides gs) {
 #define HODLR_LPF(NKSV)                                                                                       \
-  return launch_fast<TZ, SA, SB, MB, NKSV>(s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld, w_pstride,      \
+  return launch_fast<TZ, SA, SB, MB, NKSV, RP>(s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld, w_pstride,      \
                                                  node_shift, B1, ldb, kb, P, gs)
   switch (nks) {
     case 0: HODLR_LPF(0);
@@ -424,14 +467,14 @@ static hipError_t launch_fast_nks(int nks, hipStream_t s, int ntiles, int nz, in
 #undef HODLR_LPF
 }
 
-template <typename TZ, typename SA, typename SB>
+template <typename TZ, typename SA, typename SB, int RP>
 static hipError_t launch_fast_all(hipStream_t s, int ntiles, const Tile* tiles, TZ* Z, int64_t ldz, int nz,
                                   const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld, int64_t w_pstride,
                                   int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P, GroupStrides gs) {
   const int bchunks = kb > 0 ? (kb + 63) / 64 : 1;
   const int nks = ka / 4;
 #define HODLR_LPM(MBV)                                                                                            \
-  return launch_fast_nks<TZ, SA, SB, MBV>(nks, s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,           \
+  return launch_fast_nks<TZ, SA, SB, MBV, RP>(nks, s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,           \
                                                 w_pstride, node_shift, B1, ldb, kb, P, gs)
   switch (kb > 0 ? std::min(kb, 64) / 16 : 0) {
     case 0: HODLR_LPM(0);
@@ -458,9 +501,19 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int t
   // byte offsets inside a tile and chunk must stay below 2^31 for the buffer addressing
   const bool small_ld = 64 * ldz * (int64_t)sizeof(TZ) < (1ll << 31) && 64 * lda * (int64_t)sizeof(SA) < (1ll << 31) &&
                         64 * ldb * (int64_t)sizeof(SB) < (1ll << 31);
-  if (tiles_aligned && small_ld && ka % 16 == 0 && kb % 16 == 0) {
-    return launch_fast_all<TZ, SA, SB>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride, node_shift, B1,
-                                       ldb, kb, P, gs);
+  if ((tiles_aligned & 1) && small_ld && ka % 16 == 0 && kb % 16 == 0) {
+    if constexpr (sizeof(TZ) == 4) {
+      // 4-byte elements, tile heights multiples of 32, even leading dimensions and
+      // 16-byte aligned operands (every paired access is naturally aligned): two rows per lane
+      auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+      const bool pair_ok = ldz % 2 == 0 && (ka == 0 || lda % 2 == 0) && (kb == 0 || ldb % 2 == 0) && al16(Z) &&
+                           (ka == 0 || al16(A1)) && (kb == 0 || al16(B1));
+      if ((tiles_aligned & 2) && pair_ok)
+        return launch_fast_all<TZ, SA, SB, 2>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride, node_shift,
+                                              B1, ldb, kb, P, gs);
+    }
+    return launch_fast_all<TZ, SA, SB, 1>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride, node_shift, B1,
+                                          ldb, kb, P, gs);
   }
   const int mbn = kb > 0 ? (min(kb, 64) + 15) / 16 : 1;
   const size_t smem_red = kb > 0 ? sizeof(TZ) * 4 * 16 * mbn * 64 : 0;

@@ -65,6 +65,44 @@ struct Buf<float> {
   }
 };
 
+// Two consecutive elements per lane (one 8- or 16-byte access).
+template <typename T>
+struct Buf2;
+template <>
+struct Buf2<float> {
+  typedef float P __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, float& x0, float& x1) {
+    const P p = __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, 0));
+    x0 = p[0];
+    x1 = p[1];
+  }
+  static __device__ __forceinline__ void store(float x0, float x1, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    using U = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    P p;
+    p[0] = x0;
+    p[1] = x1;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, p), r, (int)v, (int)s, 0);
+  }
+};
+template <>
+struct Buf2<double> {
+  typedef double P __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, double& x0,
+                                              double& x1) {
+    const P p = __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b128(r, (int)v, (int)s, 0));
+    x0 = p[0];
+    x1 = p[1];
+  }
+  static __device__ __forceinline__ void store(double x0, double x1, __amdgpu_buffer_rsrc_t r, uint32_t v,
+                                               uint32_t s) {
+    using U = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+    P p;
+    p[0] = x0;
+    p[1] = x1;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, p), r, (int)v, (int)s, 0);
+  }
+};
+
 template <typename V>
 __device__ __forceinline__ V vzero() {
   V v;
