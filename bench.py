@@ -37,7 +37,7 @@ PEAK = dict(hbm=8.0e12, f64=78.6e12, f32=157.3e12, bf16=2.5e15)
 # reads back; summary and commands in profiles/level_pass_traffic_n1m_fp64.md).
 # It is reported only while the kernel source is the one it was measured on.
 LEVEL_PASS_TRAFFIC = dict(
-    source_sha256="b338bd377a08a7f48f72049580363a39f1072acf4c3daa5159e457467dc2f374",
+    source_sha256="fdc30a8fc87fa87d5814ea80c0f1fb9946f9b6c3ba356b3ab3e5f18e505f7208",
     n=1 << 20, leaf=256, rank=32, bytes_per_launch=4.26e9)
 
 
