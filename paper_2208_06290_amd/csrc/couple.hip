@@ -30,33 +30,43 @@ namespace hodlr {
 // ---------------------------------------------------------------------------
 // segment sums: out[s] = sum of tiles [desc[s].x, desc[s].x + desc[s].y)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NT>
 __global__ void segment_reduce_kernel(const int2* __restrict__ desc, int64_t elems, const T* __restrict__ P,
                                       T* __restrict__ out) {
   const int sg = blockIdx.y;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= elems) return;
-  const int2 d = desc[sg];  // d.y <= kSegTiles items
+  const int2 d = desc[sg];  // d.y <= NT items
   // all loads in flight at once (clamped to the segment), summed in item order
-  T v[kSegTiles];
+  T v[NT];
 #pragma unroll
-  for (int t = 0; t < kSegTiles; ++t) v[t] = P[(int64_t)(d.x + min(t, d.y - 1)) * elems + e];
+  for (int t = 0; t < NT; ++t) v[t] = P[(int64_t)(d.x + min(t, d.y - 1)) * elems + e];
   T acc = v[0];
 #pragma unroll
-  for (int t = 1; t < kSegTiles; ++t)
+  for (int t = 1; t < NT; ++t)
     if (t < d.y) acc += v[t];
   out[(int64_t)sg * elems + e] = acc;
 }
 
+// maxy: largest item count of a segment (<= kSegTiles); the kernel issues that many loads
 template <typename T>
-hipError_t launch_segment_reduce(hipStream_t s, int nsegs, const int2* d_desc, int64_t elems, const T* P, T* out) {
+hipError_t launch_segment_reduce(hipStream_t s, int nsegs, const int2* d_desc, int64_t elems, const T* P, T* out,
+                                 int maxy) {
   if (nsegs == 0 || elems == 0) return hipSuccess;
+  if (maxy < 1 || maxy > kSegTiles) return hipErrorInvalidValue;
   dim3 grid((unsigned)((elems + 255) / 256), (unsigned)nsegs);
-  hipLaunchKernelGGL(segment_reduce_kernel<T>, grid, dim3(256), 0, s, d_desc, elems, P, out);
+  if (maxy <= 2)
+    hipLaunchKernelGGL((segment_reduce_kernel<T, 2>), grid, dim3(256), 0, s, d_desc, elems, P, out);
+  else if (maxy <= 4)
+    hipLaunchKernelGGL((segment_reduce_kernel<T, 4>), grid, dim3(256), 0, s, d_desc, elems, P, out);
+  else if (maxy <= 8)
+    hipLaunchKernelGGL((segment_reduce_kernel<T, 8>), grid, dim3(256), 0, s, d_desc, elems, P, out);
+  else
+    hipLaunchKernelGGL((segment_reduce_kernel<T, kSegTiles>), grid, dim3(256), 0, s, d_desc, elems, P, out);
   return hipGetLastError();
 }
-template hipError_t launch_segment_reduce<double>(hipStream_t, int, const int2*, int64_t, const double*, double*);
-template hipError_t launch_segment_reduce<float>(hipStream_t, int, const int2*, int64_t, const float*, float*);
+template hipError_t launch_segment_reduce<double>(hipStream_t, int, const int2*, int64_t, const double*, double*, int);
+template hipError_t launch_segment_reduce<float>(hipStream_t, int, const int2*, int64_t, const float*, float*, int);
 
 // sum over the segments of `node`: element (i, c) of an r x ncols col-major block
 template <typename T>

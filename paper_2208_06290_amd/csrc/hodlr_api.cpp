@@ -125,6 +125,7 @@ struct DevMem {
 // node has a single sum left, which the coupling kernels read.
 struct ProdStage {
   int nsegs = 0;
+  int maxy = 0;            // largest item count of a segment
   int2* d_desc = nullptr;  // per output segment: first input item, count
 };
 struct ProdPlan {
@@ -278,6 +279,7 @@ hodlr_status make_prod(hodlr_factors* F, int q, int p, hipStream_t st) {
     nstart[pp.nnodes] = (int)desc.size();
     ProdStage ps;
     ps.nsegs = (int)desc.size();
+    for (const int2& d : desc) ps.maxy = std::max(ps.maxy, d.y);
     hodlr_status s = F->mem.alloc(&ps.d_desc, desc.size());
     if (s) return s;
     if (hipMemcpy(ps.d_desc, desc.data(), desc.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
@@ -428,7 +430,8 @@ hodlr_status prod_segments(hodlr_factors* F, hipStream_t st, int q, int p, int64
   T* region[2] = {segbuf, segbuf + pp.buf_items[0] * elems};
   for (size_t k = 0; k < pp.stages.size(); ++k) {
     T* out = region[k & 1];
-    HL("segment_reduce", launch_segment_reduce<T>(st, pp.stages[k].nsegs, pp.stages[k].d_desc, elems, in, out));
+    HL("segment_reduce", launch_segment_reduce<T>(st, pp.stages[k].nsegs, pp.stages[k].d_desc, elems, in, out,
+                                                  pp.stages[k].maxy));
     in = out;
   }
   *segs = in;

@@ -102,9 +102,11 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int t
                              int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
                              GroupStrides gs = GroupStrides());
 
-// Segment sums of tile partials: out[s] = sum of tiles [desc[s].x, desc[s].x + desc[s].y).
+// Segment sums of tile partials: out[s] = sum of tiles [desc[s].x, desc[s].x + desc[s].y),
+// maxy = max over s of desc[s].y (<= kSegTiles).
 template <typename T>
-hipError_t launch_segment_reduce(hipStream_t s, int nsegs, const int2* d_desc, int64_t elems, const T* P, T* out);
+hipError_t launch_segment_reduce(hipStream_t s, int nsegs, const int2* d_desc, int64_t elems, const T* P, T* out,
+                                 int maxy);
 
 // Coupling systems with 2r <= 64 and 2r % 16 == 0 are inverted explicitly
 // (Gauss-Jordan with partial pivoting): the factor stores K^{-1} (2r x 2r,
