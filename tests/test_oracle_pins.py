@@ -313,6 +313,99 @@ def test_refinement_reports_non_convergence():
     assert not ok
 
 
+# ---- the refinement helpers: relres, bf16 rounding, the low-precision solver -------------
+
+def _relres_by_dense(H, X, B):
+    """max over columns j of ||b_j - A x_j||_2 / ||b_j||_2 with A assembled densely
+    (the relative residual of the paper's results tables, per column)."""
+    A = O.assemble_dense(H)
+    out = 0.0
+    for j in range(B.shape[1]):
+        out = max(out, np.linalg.norm(B[:, j] - A @ X[:, j]) / np.linalg.norm(B[:, j]))
+    return out
+
+
+def _relres_case():
+    H = _case(CASES[2], seed=21)
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((H.N, 3)) * np.array([1e-3, 1.0, 1e4])
+    # residuals of very different relative size per column, so a sum over
+    # columns, a Frobenius norm or a squared denominator gives another value
+    E = rng.standard_normal((H.N, 3)) * np.array([1e-9, 1e-4, 1e-2])
+    B = O.assemble_dense(H) @ X + E
+    return H, X, B
+
+
+def _check_relres(fn):
+    # the residual of the 1e4-scaled column cancels to 1e-2 of its terms, so
+    # the two evaluations agree to about 1e-10 relative, not to the last bit
+    H, X, B = _relres_case()
+    return abs(fn(H, X, B) - _relres_by_dense(H, X, B)) <= 1e-7 * _relres_by_dense(H, X, B)
+
+
+def test_relres_is_the_largest_column_residual():
+    assert _check_relres(O.relres)
+    H, X, B = _relres_case()
+    # one right-hand side given as a vector
+    assert O.relres(H, X[:, 1], B[:, 1]) == pytest.approx(_relres_by_dense(H, X[:, 1:2], B[:, 1:2]), rel=1e-7)
+
+
+@pytest.mark.parametrize("mistake", ["squared", "colsum", "frobenius", "noabs_b"])
+def test_planted_relres_mistakes_fail_the_pin(mistake):
+    def bad(H, X, B):
+        Rm = B - O.matvec(H, X)
+        if mistake == "squared":
+            return float(np.max(np.linalg.norm(Rm, axis=0) / np.linalg.norm(B, axis=0) ** 2))
+        if mistake == "colsum":
+            return float(np.sum(np.linalg.norm(Rm, axis=0) / np.linalg.norm(B, axis=0)))
+        if mistake == "frobenius":
+            return float(np.linalg.norm(Rm) / np.linalg.norm(B))
+        return float(np.max(np.linalg.norm(Rm, axis=0) / np.abs(B).max(axis=0)))
+    assert not _check_relres(bad)
+
+
+def test_bf16_rounding_fixed_points():
+    """bfloat16 keeps 8 significant bits: at 1 the spacing is 2^-7, ties go to
+    the even significand (IEEE round to nearest even)."""
+    x = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 3 * 2.0 ** -8), 1 + 2.0 ** -8 + 2.0 ** -20,
+                  1 + 2.0 ** -7, 3.0, -0.0, 2.0 ** -130], dtype=np.float32)
+    want = np.array([1.0, 1 + 2.0 ** -6, -(1 + 2.0 ** -6), 1 + 2.0 ** -7, 1 + 2.0 ** -7, 3.0, -0.0,
+                     2.0 ** -130], dtype=np.float32)
+    got = OH._round_bf16(x)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_bf16_rounding_matches_torch_conversion():
+    rng = np.random.default_rng(22)
+    v = (rng.standard_normal(200000) * np.exp2(rng.integers(-100, 100, 200000))).astype(np.float32)
+    got = OH._round_bf16(v)
+    assert np.all(got.view(np.uint32) & 0xFFFF == 0)
+    ref = torch.from_numpy(v).to(torch.bfloat16).float().numpy()
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(OH._round_bf16(got).view(np.uint32), got.view(np.uint32))  # representable: unchanged
+
+
+@pytest.mark.parametrize("prec,lo,hi", [("fp32", 1e-10, 1e-5), ("bf16", 1e-4, 5e-2)])
+def test_low_precision_solver_really_rounds(prec, lo, hi):
+    """The emulated low-precision solve must be off from the FP64 solution by
+    about the unit roundoff times the condition number: far more than FP64
+    rounding (else nothing was rounded) and within kappa times the format's
+    error (else the solve is wrong)."""
+    H = _mk(1024, 64, 12, seed=23)
+    A = O.assemble_dense(H)
+    kappa = np.linalg.cond(A)
+    b = np.random.default_rng(23).standard_normal(H.N)
+    x = np.linalg.solve(A, b)
+    xl = O.low_precision_solver(H, prec)(b)
+    err = _rel(xl, x)
+    assert lo < err < kappa * hi, (err, kappa)
+    if prec == "bf16":
+        # the solver's matrix is the one with every entry of D, U, V rounded
+        Hr = O.Hodlr(H.offsets, H.ranks, *(OH._round_bf16(M.astype(np.float32)).astype(np.float64)
+                                           for M in (H.D, H.U, H.V)))
+        assert _rel(xl, np.linalg.solve(O.assemble_dense(Hr), b)) < kappa * 1e-5
+
+
 # ---- singular inputs ------------------------------------------------------------------
 
 def test_singular_leaf_is_reported():
