@@ -21,6 +21,12 @@
  * Streams: every call is ordered on `stream` (a hipStream_t; NULL = the
  * null stream).  Calls that return a convergence or singularity verdict
  * synchronise `stream` once per verdict; all others are asynchronous.
+ * A factorization keeps one solve workspace per stream it is used on, so
+ * hodlr_solve, hodlr_solve_adjoint and hodlr_grad may run concurrently on
+ * different streams (and from different host threads) on one factorization;
+ * calls on one stream are ordered by the stream.  hodlr_refactor waits (on
+ * the device) for the last call on every stream before it overwrites the
+ * factors, and later calls wait for it.
  *
  * Errors: negative status = invalid argument / resource error, detected
  * before any kernel is launched where possible; nothing is written then.
@@ -57,6 +63,18 @@ typedef enum {
 #define HODLR_MAX_RANK 64      /* largest per-level rank r_l                    */
 #define HODLR_MAX_LEVELS 24
 
+/* Flags of hodlr_factor.
+ * HODLR_INPLACE: the factorization overwrites the caller's matrix, as in
+ *   Section III-B (the leaf LU factors replace D_big, Y_big replaces U_big):
+ *   the leaf factors of leaf a go to rows I_a of D (ld ldd; needs
+ *   |I_a| % 16 == 0 for every leaf), Y_big to U (column-major, ld ldu), and
+ *   the factors need the storage type to be the compute type (F64 storage
+ *   with F64, F32 storage with F32 or BF16).  D and U are then written, so
+ *   refinement (opts->refine) and hodlr_grad, which need the original
+ *   matrix, return HODLR_ERR_ARG on such a factorization.  V is only read.
+ *   Without the flag D, U and V are only read and must outlive the factors. */
+#define HODLR_INPLACE 1
+
 /* A HODLR matrix (inputs of the factorization; Alg. "a:gpuf" "Require").
  *   n             N >= 1
  *   levels        L >= 0; the tree has 2^L leaves
@@ -64,13 +82,15 @@ typedef enum {
  *                 node i of level l spans leaves [i 2^{L-l}, (i+1) 2^{L-l}).
  *                 NULL = uniform tree (requires 2^L | N).
  *   ranks         host, L entries, ranks[l-1] = r_l, 0 <= r_l <= HODLR_MAX_RANK
- *                 and r_l <= size of every level-l node.  May be NULL if L = 0.
+ *                 and r_l <= size of every level-l node (else HODLR_ERR_ARG).
+ *                 May be NULL if L = 0.
  *   dtype         storage type of D, U, V: HODLR_F64 or HODLR_F32
  *   D, ldd        N x m_max (m_max = largest leaf), ldd >= N
  *   U, ldu        N x R (R = R_L), ldu >= N (ignored if R = 0)
  *   V, ldv        N x R, ldv >= N
- * The library only reads D, U, V.  A factorization keeps referring to them
- * (refinement residuals and gradients), so they must outlive it unchanged. */
+ * The library only reads D, U, V (unless hodlr_factor is given
+ * HODLR_INPLACE).  A factorization keeps referring to them (refinement
+ * residuals and gradients), so they must outlive it unchanged. */
 typedef struct {
   int64_t n;
   int32_t levels;
@@ -124,16 +144,19 @@ typedef struct {
  * Y_big(:, 1:R_l) (eqs. "e:node1", "e:node2").
  *   A        the matrix (see hodlr_matrix)
  *   compute  HODLR_F64 (requires dtype F64), HODLR_F32 or HODLR_BF16
+ *   flags    0 or HODLR_INPLACE (other bits: HODLR_ERR_ARG)
  *   F        out: new factorization object (NULL on negative status)
  * Returns HODLR_ERR_SINGULAR (factors kept but unusable; *info filled if
  * info != NULL) when a pivot is exactly zero.  Synchronises the stream once
  * (singularity verdict).  Allocates device memory (hipMalloc). */
-hodlr_status hodlr_factor(const hodlr_matrix *A, hodlr_dtype compute, void *stream,
+hodlr_status hodlr_factor(const hodlr_matrix *A, hodlr_dtype compute, int32_t flags, void *stream,
                           hodlr_factors **F, hodlr_info *info);
 
 /* Recompute the factorization in F's storage for new values of D, U, V
  * with exactly the same tree, ranks, storage type and leading dimensions
- * (pointers may change).  Allocates nothing.  Same verdicts as hodlr_factor. */
+ * (pointers may change; an in-place factorization then overwrites the new
+ * D and U).  Allocates nothing.  Same verdicts as hodlr_factor.  Must not be
+ * called from one host thread while another host thread calls into F. */
 hodlr_status hodlr_refactor(hodlr_factors *F, const hodlr_matrix *A, void *stream, hodlr_info *info);
 
 /* Solution (Alg. "a:solve" / Alg. "a:gpus"): B <- A^{-1} B in place
@@ -174,10 +197,13 @@ hodlr_status hodlr_grad(const hodlr_factors *F, int64_t nrhs, const double *X, i
  * eq. "e:recursion") into Y as FP64 (ldy >= N). */
 hodlr_status hodlr_factors_y(const hodlr_factors *F, double *Y, int64_t ldy, void *stream);
 
-/* Device bytes owned by F. */
+/* Device bytes owned by F: the factors, the factorization's workspace and
+ * the solve workspaces of every stream F was used on. */
 size_t hodlr_factor_bytes(const hodlr_factors *F);
 
-/* Release F (waits for its pending work). NULL is ignored. */
+/* Release F.  Waits for F's own pending work only (the factorization and
+ * the last call on each stream that used F), not for the whole device.
+ * NULL is ignored. */
 void hodlr_destroy(hodlr_factors *F);
 
 const char *hodlr_status_string(hodlr_status s);

@@ -9,7 +9,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <climits>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -136,6 +138,28 @@ struct ProdPlan {
   int32_t* d_seg_start = nullptr;
 };
 
+// Solve-side workspace of one stream: tile partials, segment sums, W, the
+// compute-type copy of the right-hand sides, refinement vectors, projection
+// trees and norms for up to `nrhs` columns.  Calls on different streams use
+// different workspaces, so they may run concurrently on one factorization;
+// calls on one stream are ordered by the stream.
+struct Workspace {
+  hipStream_t stream = nullptr;
+  std::mutex mu;  // one host call at a time on this stream
+  DevMem mem;
+  int nrhs = -1;
+  void* sP = nullptr;
+  void* sseg = nullptr;
+  void* sw = nullptr;
+  void* sx = nullptr;      // compute-type copy of the right-hand sides
+  double* rx = nullptr;    // refinement: iterate x
+  double* rr = nullptr;    // refinement: residual
+  double* tree = nullptr;  // matvec projection tree
+  double* tree2 = nullptr;
+  double* nrm = nullptr;       // norms: part | b2 | r2 | rinf
+  hipEvent_t done = nullptr;   // recorded after the last call's work on `stream`
+};
+
 }  // namespace
 
 struct hodlr_factors {
@@ -150,6 +174,7 @@ struct hodlr_factors {
   std::vector<int> ranks;  // r_1..r_L
   std::vector<int> Rp;     // R_0..R_L
   hodlr_dtype storage = HODLR_F64, compute = HODLR_F64;
+  int inplace = 0;  // HODLR_INPLACE: LU in the caller's D, Y in the caller's U
   // the caller's matrix
   const void *D = nullptr, *U = nullptr, *V = nullptr;
   int64_t ldd = 0, ldu = 0, ldv = 0;
@@ -167,6 +192,7 @@ struct hodlr_factors {
   // factors (T = compute element type)
   size_t tsize = 8;
   void* lu = nullptr;
+  int64_t lul = 0;  // leading dimension of the leaf factors (ldl, or ldd in place)
   int32_t* piv = nullptr;
   int32_t* perm = nullptr;
   void* udinv = nullptr;
@@ -183,19 +209,10 @@ struct hodlr_factors {
   void* P = nullptr;
   void* segbuf = nullptr;
   unsigned long long* d_info = nullptr;
-  // solve / matvec / refinement workspace, grown on demand
-  DevMem ws;
-  int ws_nrhs = -1;
-  void* sP = nullptr;
-  void* sseg = nullptr;
-  void* sw = nullptr;
-  void* sx = nullptr;      // compute-type copy of the right-hand sides
-  double* rx = nullptr;    // refinement: iterate x
-  double* rr = nullptr;    // refinement: residual
-  double* tree = nullptr;  // matvec projection tree
-  double* tree2 = nullptr;
-  double* nrm = nullptr;   // norms: part | b2 | r2 | rinf
-  std::mutex mu;
+  // solve / matvec / refinement workspaces, one per stream, grown on demand
+  std::mutex mu;  // guards wsmap; held by refactor for its whole enqueue
+  std::map<hipStream_t, std::unique_ptr<Workspace>> wsmap;
+  hipEvent_t ready = nullptr;  // recorded after the factorization's last kernel
 };
 
 namespace {
@@ -230,6 +247,18 @@ hodlr_status validate(const hodlr_matrix* A, std::vector<int64_t>& off, std::vec
     if (A->ranks[l] < 0) return HODLR_ERR_ARG;
     if (A->ranks[l] > HODLR_MAX_RANK) return HODLR_ERR_UNSUPPORTED;
     ranks[l] = A->ranks[l];
+  }
+  // every level-l node must hold at least r_l rows (its generators are |I_a| x r_l
+  // with r_l independent columns); node sizes by pairwise sums from the leaves
+  {
+    std::vector<int64_t> sz(nl);
+    for (int64_t i = 0; i < nl; ++i) sz[i] = off[i + 1] - off[i];
+    for (int l = L; l >= 1; --l) {
+      int64_t mn = INT64_MAX;
+      for (int64_t i = 0; i < (int64_t(1) << l); ++i) mn = std::min(mn, sz[i]);
+      if (ranks[l - 1] > mn) return HODLR_ERR_ARG;
+      for (int64_t i = 0; i < (int64_t(1) << (l - 1)); ++i) sz[i] = sz[2 * i] + sz[2 * i + 1];
+    }
   }
   if (A->dtype != HODLR_F64 && A->dtype != HODLR_F32) return HODLR_ERR_ARG;
   int R = 0;
@@ -350,8 +379,14 @@ hodlr_status allocate_factors(hodlr_factors* F) {
   if ((s = plan(F))) return s;
   unsigned char* b;
   const size_t nl = F->nleaf, mm = F->ldl;
-  if ((s = M.alloc(&b, nl * mm * mm * ts))) return s;
-  F->lu = b;
+  if (F->inplace) {
+    F->lu = const_cast<void*>(F->D);  // the leaf factors overwrite the caller's D
+    F->lul = F->ldd;
+  } else {
+    if ((s = M.alloc(&b, nl * mm * mm * ts))) return s;
+    F->lu = b;
+    F->lul = F->ldl;
+  }
   if ((s = M.alloc(&F->piv, nl * mm))) return s;
   if ((s = M.alloc(&F->perm, nl * mm))) return s;
   if ((s = M.alloc(&b, nl * mm * ts))) return s;
@@ -361,17 +396,23 @@ hodlr_status allocate_factors(hodlr_factors* F) {
   // Y in the row-group blocked layout (each 256-row group of all R columns
   // contiguous) when no leaf and no tile crosses a 256-row boundary, else
   // column-major with leading dimension N
-  bool blocked = F->R > 0;
+  bool blocked = F->R > 0 && !F->inplace;  // in place, Y is column-major in the caller's U
   for (int a = 0; a < F->nleaf && blocked; ++a)
     if ((F->off[a] >> 8) != ((F->off[a + 1] - 1) >> 8)) blocked = false;
   for (int q = 0; q <= L && blocked; ++q)
     for (const Tile& t : F->h_tiles[q])
       if ((t.row0 >> 8) != ((t.row0 + t.nrows - 1) >> 8)) blocked = false;
   const int64_t ngroups = (F->n + 255) / 256;
-  F->ldy = blocked ? 256 : F->n;
-  F->gsy = blocked ? 256 * (int64_t)F->R : 256;
-  if ((s = M.alloc(&b, (size_t)(blocked ? ngroups * 256 : F->n) * F->R * ts))) return s;
-  F->Y = b;
+  if (F->inplace) {
+    F->Y = const_cast<void*>(F->U);
+    F->ldy = F->ldu;
+    F->gsy = 256;
+  } else {
+    F->ldy = blocked ? 256 : F->n;
+    F->gsy = blocked ? 256 * (int64_t)F->R : 256;
+    if ((s = M.alloc(&b, (size_t)(blocked ? ngroups * 256 : F->n) * F->R * ts))) return s;
+    F->Y = b;
+  }
   F->koff.assign(L + 1, 0);
   F->kvoff.assign(L + 1, 0);
   F->kioff.assign(L + 1, 0);
@@ -413,6 +454,7 @@ hodlr_status allocate_factors(hodlr_factors* F) {
   if ((s = M.alloc(&b, segmax * ts))) return s;
   F->segbuf = b;
   if ((s = M.alloc(&F->d_info, 2))) return s;
+  if (hipEventCreateWithFlags(&F->ready, hipEventDisableTiming) != hipSuccess) return HODLR_ERR_HIP;
   return HODLR_OK;
 }
 
@@ -448,11 +490,11 @@ hodlr_status run_factor(hodlr_factors* F, hipStream_t st) {
   const S* U = static_cast<const S*>(F->U);
   const S* V = static_cast<const S*>(F->V);
   if (hipMemsetAsync(F->d_info, 0xFF, 2 * sizeof(unsigned long long), st) != hipSuccess) return HODLR_ERR_HIP;
-  HL("leaf_lu", (launch_leaf_lu<T, S>(st, F->nleaf, F->ldl, F->d_off, D, F->ldd, tp<T>(F->lu), F->piv, F->perm,
-                                      tp<T>(F->udinv), tp<T>(F->invl), F->d_info)));
+  HL("leaf_lu", (launch_leaf_lu<T, S>(st, F->nleaf, F->ldl, F->d_off, D, F->ldd, tp<T>(F->lu), F->lul, F->inplace,
+                                      F->piv, F->perm, tp<T>(F->udinv), tp<T>(F->invl), F->d_info)));
   if (F->R > 0)
-    HL("leaf_trsm", (launch_leaf_trsm<T, S>(st, 0, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->perm,
-                                            tp<T>(F->invl), U, F->ldu, Y, F->ldy, F->R, 256, F->gsy)));
+    HL("leaf_trsm", (launch_leaf_trsm<T, S>(st, 0, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->lul, F->inplace,
+                                            F->perm, tp<T>(F->invl), U, F->ldu, Y, F->ldy, F->R, 256, F->gsy)));
   if (L > 0) {
     // products V^T Y for the children of level L-1 (the leaves)
     HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], F->tiles_aligned[L], Y, F->ldy, F->R,
@@ -530,56 +572,81 @@ hodlr_status dispatch_factor(hodlr_factors* F, hipStream_t st) {
 }
 
 // ---- solve-side workspace --------------------------------------------------
-hodlr_status ensure_ws(hodlr_factors* F, int nrhs) {
-  if (nrhs <= F->ws_nrhs) return HODLR_OK;
-  F->ws.release();
-  F->ws_nrhs = -1;
+// The workspace of stream st (created on first use).
+Workspace* get_ws(hodlr_factors* F, hipStream_t st) {
+  std::lock_guard<std::mutex> g(F->mu);
+  auto it = F->wsmap.find(st);
+  if (it != F->wsmap.end()) return it->second.get();
+  std::unique_ptr<Workspace> w(new Workspace());
+  w->stream = st;
+  if (hipEventCreateWithFlags(&w->done, hipEventDisableTiming) != hipSuccess) return nullptr;
+  Workspace* p = w.get();
+  F->wsmap[st] = std::move(w);
+  return p;
+}
+
+// Sizes of the solve-side buffers for nrhs columns (elements).
+struct WsSizes {
+  size_t pmax = 0, segmax = 0, wmax = 0, n = 0, treeN = 0, nrm = 0;
+};
+WsSizes ws_sizes(const hodlr_factors* F, int nrhs) {
+  WsSizes z;
   const int L = F->L;
-  const size_t ts = F->tsize;
-  size_t pmax = 0, segmax = 0, wmax = 0;
   for (int p = 1; p <= L; ++p) {
     const size_t elems = (size_t)F->ranks[p - 1] * nrhs;
     for (int q : {fwd_prod_tiles(F, p), adj_prod_tiles(F, p)}) {
-      pmax = std::max(pmax, (size_t)F->ntiles[q] * elems);
-      const ProdPlan& pp = F->prods[{q, p}];
-      segmax = std::max(segmax, (pp.buf_items[0] + pp.buf_items[1]) * elems);
+      z.pmax = std::max(z.pmax, (size_t)F->ntiles[q] * elems);
+      const ProdPlan& pp = F->prods.at({q, p});
+      z.segmax = std::max(z.segmax, (pp.buf_items[0] + pp.buf_items[1]) * elems);
     }
   }
-  for (int p = 0; p < L; ++p) wmax = std::max(wmax, (size_t)(int64_t(1) << p) * 2 * F->ranks[p] * nrhs);
-  const size_t n = (size_t)F->n * nrhs;
-  const size_t treeN = (((size_t)1 << (L + 1)) - 2) * (size_t)std::max(F->R, 1) * nrhs;
+  for (int p = 0; p < L; ++p) z.wmax = std::max(z.wmax, (size_t)(int64_t(1) << p) * 2 * F->ranks[p] * nrhs);
+  z.n = (size_t)F->n * nrhs;
+  z.treeN = std::max<size_t>((((size_t)1 << (L + 1)) - 2) * (size_t)std::max(F->R, 1) * nrhs, 1);
+  z.nrm = (size_t)nrhs * (2 * 256 + 8);
+  return z;
+}
+
+hodlr_status ensure_ws(hodlr_factors* F, Workspace& W, int nrhs) {
+  if (nrhs <= W.nrhs) return HODLR_OK;
+  // the old buffers may still be read by queued work of this stream
+  if (W.nrhs >= 0 && hipStreamSynchronize(W.stream) != hipSuccess) return HODLR_ERR_HIP;
+  W.mem.release();
+  W.nrhs = -1;
+  const size_t ts = F->tsize;
+  const WsSizes z = ws_sizes(F, nrhs);
   unsigned char* b;
   hodlr_status s;
-  DevMem& M = F->ws;
-  if ((s = M.alloc(&b, pmax * ts))) return s;
-  F->sP = b;
-  if ((s = M.alloc(&b, segmax * ts))) return s;
-  F->sseg = b;
-  if ((s = M.alloc(&b, wmax * ts))) return s;
-  F->sw = b;
-  if ((s = M.alloc(&b, n * ts))) return s;
-  F->sx = b;
-  if ((s = M.alloc(&F->rx, n))) return s;
-  if ((s = M.alloc(&F->rr, n))) return s;
-  if ((s = M.alloc(&F->tree, std::max<size_t>(treeN, 1)))) return s;
-  if ((s = M.alloc(&F->tree2, std::max<size_t>(treeN, 1)))) return s;
-  if ((s = M.alloc(&F->nrm, (size_t)nrhs * (2 * 256 + 8)))) return s;
-  F->ws_nrhs = nrhs;
+  DevMem& M = W.mem;
+  if ((s = M.alloc(&b, z.pmax * ts))) return s;
+  W.sP = b;
+  if ((s = M.alloc(&b, z.segmax * ts))) return s;
+  W.sseg = b;
+  if ((s = M.alloc(&b, z.wmax * ts))) return s;
+  W.sw = b;
+  if ((s = M.alloc(&b, z.n * ts))) return s;
+  W.sx = b;
+  if ((s = M.alloc(&W.rx, z.n))) return s;
+  if ((s = M.alloc(&W.rr, z.n))) return s;
+  if ((s = M.alloc(&W.tree, z.treeN))) return s;
+  if ((s = M.alloc(&W.tree2, z.treeN))) return s;
+  if ((s = M.alloc(&W.nrm, z.nrm))) return s;
+  W.nrhs = nrhs;
   return HODLR_OK;
 }
 
 // x <- A^{-1} x (trans = 0) or A^{-T} x (trans = 1) in the compute precision, x: N x nrhs, ld N
 template <typename T, typename S>
-hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs, T* X, int64_t ldx) {
+hodlr_status apply_inverse(hodlr_factors* F, Workspace& Wk, hipStream_t st, int trans, int nrhs, T* X, int64_t ldx) {
   const int L = F->L;
   const int64_t N = F->n;
   const T* Y = tp<T>(F->Y);
   const S* V = static_cast<const S*>(F->V);
-  T* P = tp<T>(F->sP);
-  T* w = tp<T>(F->sw);
+  T* P = tp<T>(Wk.sP);
+  T* w = tp<T>(Wk.sw);
   if (!trans) {
-    HL("leaf_solve", (launch_leaf_trsm<T, T>(st, 0, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->perm,
-                                             tp<T>(F->invl), X, ldx, X, ldx, nrhs)));
+    HL("leaf_solve", (launch_leaf_trsm<T, T>(st, 0, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->lul, F->inplace,
+                                             F->perm, tp<T>(F->invl), X, ldx, X, ldx, nrhs)));
     if (L == 0) return HODLR_OK;
     HL("solve_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], F->tiles_aligned[L], X, ldx, nrhs, (const T*)nullptr, N,
                                                  0, (const T*)nullptr, 0, 0, 0, V + (int64_t)F->Rp[L - 1] * F->ldv,
@@ -590,7 +657,7 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
       if (r > 0) {
         const T* segs;
         const int32_t* seg_start;
-        hodlr_status s = prod_segments<T>(F, st, fwd_prod_tiles(F, q), q, (int64_t)r * nrhs, P, tp<T>(F->sseg),
+        hodlr_status s = prod_segments<T>(F, st, fwd_prod_tiles(F, q), q, (int64_t)r * nrhs, P, tp<T>(Wk.sseg),
                                           &segs, &seg_start);
         if (s) return s;
         HL("couple_solve", (launch_couple_solve<T>(st, 0, 1 << p, r, kpad(r), nrhs, segs, seg_start,
@@ -618,7 +685,7 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
       if (r > 0) {
         const T* segs;
         const int32_t* seg_start;
-        hodlr_status s = prod_segments<T>(F, st, adj_prod_tiles(F, q), q, (int64_t)r * nrhs, P, tp<T>(F->sseg),
+        hodlr_status s = prod_segments<T>(F, st, adj_prod_tiles(F, q), q, (int64_t)r * nrhs, P, tp<T>(Wk.sseg),
                                           &segs, &seg_start);
         if (s) return s;
         HL("couple_solve_t", (launch_couple_solve<T>(st, 1, 1 << p, r, kpad(r), nrhs, segs, seg_start,
@@ -635,8 +702,8 @@ hodlr_status apply_inverse(hodlr_factors* F, hipStream_t st, int trans, int nrhs
                                                      GroupStrides{256, 256, F->gsy})));
     }
   }
-  HL("leaf_solve_t", (launch_leaf_trsm<T, T>(st, 1, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->perm,
-                                             tp<T>(F->invl), X, ldx, X, ldx, nrhs)));
+  HL("leaf_solve_t", (launch_leaf_trsm<T, T>(st, 1, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->lul, F->inplace,
+                                             F->perm, tp<T>(F->invl), X, ldx, X, ldx, nrhs)));
   return HODLR_OK;
 }
 
@@ -677,22 +744,21 @@ hodlr_status matvec_dispatch(hodlr_factors* F, hipStream_t st, int trans, int nr
 }
 
 template <typename T>
-hodlr_status inverse_dispatch(hodlr_factors* F, hipStream_t st, int trans, int nrhs, T* X, int64_t ldx) {
+hodlr_status inverse_dispatch(hodlr_factors* F, Workspace& Wk, hipStream_t st, int trans, int nrhs, T* X,
+                              int64_t ldx) {
   // FP64 factors exist only for FP64 storage (checked at factorization)
   if constexpr (sizeof(T) == 8) {
-    return apply_inverse<double, double>(F, st, trans, nrhs, X, ldx);
+    return apply_inverse<double, double>(F, Wk, st, trans, nrhs, X, ldx);
   } else {
-    if (F->storage == HODLR_F64) return apply_inverse<float, double>(F, st, trans, nrhs, X, ldx);
-    return apply_inverse<float, float>(F, st, trans, nrhs, X, ldx);
+    if (F->storage == HODLR_F64) return apply_inverse<float, double>(F, Wk, st, trans, nrhs, X, ldx);
+    return apply_inverse<float, float>(F, Wk, st, trans, nrhs, X, ldx);
   }
 }
 
 template <typename T>
-hodlr_status solve_impl(hodlr_factors* F, int trans, int nrhs, double* B, int64_t ldb, const hodlr_solve_opts* o,
-                        hipStream_t st, hodlr_solve_stats* stt) {
+hodlr_status solve_impl(hodlr_factors* F, Workspace& Wk, int trans, int nrhs, double* B, int64_t ldb,
+                        const hodlr_solve_opts* o, hipStream_t st, hodlr_solve_stats* stt) {
   const int64_t N = F->n;
-  hodlr_status s = ensure_ws(F, nrhs);
-  if (s) return s;
   if (stt) {
     stt->iters = 0;
     stt->converged = 1;
@@ -700,10 +766,10 @@ hodlr_status solve_impl(hodlr_factors* F, int trans, int nrhs, double* B, int64_
   }
   const bool refine = o && o->refine;
   if (!refine) {
-    if (sizeof(T) == 8) return inverse_dispatch<T>(F, st, trans, nrhs, reinterpret_cast<T*>(B), ldb);
-    T* x = tp<T>(F->sx);
+    if (sizeof(T) == 8) return inverse_dispatch<T>(F, Wk, st, trans, nrhs, reinterpret_cast<T*>(B), ldb);
+    T* x = tp<T>(Wk.sx);
     HL("convert", (launch_convert<T, double>(st, N, nrhs, B, ldb, x, N)));
-    s = inverse_dispatch<T>(F, st, trans, nrhs, x, N);
+    hodlr_status s = inverse_dispatch<T>(F, Wk, st, trans, nrhs, x, N);
     if (s) return s;
     HL("convert", (launch_convert<double, T>(st, N, nrhs, x, N, B, ldb)));
     return HODLR_OK;
@@ -711,13 +777,14 @@ hodlr_status solve_impl(hodlr_factors* F, int trans, int nrhs, double* B, int64_
   // FP64 iterative refinement
   const double tol = o->tol > 0 ? o->tol : 1e-10;
   const int max_iter = o->max_iter > 0 ? o->max_iter : 30;
-  double* part = F->nrm;
+  double* part = Wk.nrm;
   double* b2 = part + (size_t)nrhs * 512;
   double* r2 = b2 + nrhs;
   double* rinf = r2 + nrhs;
-  double* x = F->rx;
-  double* r = F->rr;
-  T* t = tp<T>(F->sx);
+  double* x = Wk.rx;
+  double* r = Wk.rr;
+  T* t = tp<T>(Wk.sx);
+  hodlr_status s;
   HL("norms", launch_colnorms(st, N, nrhs, B, ldb, part, b2, rinf));
   if (hipMemsetAsync(x, 0, (size_t)N * nrhs * 8, st) != hipSuccess) return HODLR_ERR_HIP;
   if (hipMemcpy2DAsync(r, N * 8, B, ldb * 8, N * 8, nrhs, hipMemcpyDeviceToDevice, st) != hipSuccess)
@@ -731,10 +798,10 @@ hodlr_status solve_impl(hodlr_factors* F, int trans, int nrhs, double* B, int64_
   if (nrhs == 0) res = 0.0;
   while (res > tol && it < max_iter) {
     HL("refine_scale", (launch_scale_down<T>(st, N, nrhs, r, N, rinf, t, N)));
-    s = inverse_dispatch<T>(F, st, trans, nrhs, t, N);
+    s = inverse_dispatch<T>(F, Wk, st, trans, nrhs, t, N);
     if (s) return s;
     HL("refine_axpy", (launch_axpy_up<T>(st, N, nrhs, t, N, rinf, x, N)));
-    s = matvec_dispatch(F, st, trans, nrhs, x, N, r, N, F->tree);
+    s = matvec_dispatch(F, st, trans, nrhs, x, N, r, N, Wk.tree);
     if (s) return s;
     HL("refine_residual", launch_residual(st, N, nrhs, B, ldb, r, N));
     HL("norms", launch_colnorms(st, N, nrhs, r, N, part, r2, rinf));
@@ -760,26 +827,52 @@ hodlr_status solve_impl(hodlr_factors* F, int trans, int nrhs, double* B, int64_
   return res <= tol ? HODLR_OK : HODLR_ERR_NOT_CONVERGED;
 }
 
+// One call on stream st with that stream's workspace: waits (on the device)
+// for the factorization, runs fn, and records the workspace's done event.
+template <typename Fn>
+hodlr_status on_stream(hodlr_factors* F, hipStream_t st, int nrhs, Fn fn) {
+  Workspace* W = get_ws(F, st);
+  if (!W) return HODLR_ERR_HIP;
+  std::lock_guard<std::mutex> g(W->mu);
+  hodlr_status s = ensure_ws(F, *W, nrhs);
+  if (s) return s;
+  if (hipStreamWaitEvent(st, F->ready, 0) != hipSuccess) return HODLR_ERR_HIP;
+  s = fn(*W);
+  if (hipEventRecord(W->done, st) != hipSuccess && s >= 0) s = HODLR_ERR_HIP;
+  return s;
+}
+
 hodlr_status solve_common(const hodlr_factors* Fc, int trans, int64_t nrhs, double* B, int64_t ldb,
                           const hodlr_solve_opts* o, void* stream, hodlr_solve_stats* stt) {
   hodlr_factors* F = const_cast<hodlr_factors*>(Fc);
   if (!F || nrhs < 0 || nrhs > 65535 || (nrhs > 0 && (!B || ldb < F->n))) return HODLR_ERR_ARG;
+  if (o && o->refine && F->inplace) return HODLR_ERR_ARG;  // the residual needs the original D and U
   if (nrhs == 0) return HODLR_OK;
-  std::lock_guard<std::mutex> g(F->mu);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (F->compute == HODLR_F64) return solve_impl<double>(F, trans, (int)nrhs, B, ldb, o, st, stt);
-  return solve_impl<float>(F, trans, (int)nrhs, B, ldb, o, st, stt);
+  return on_stream(F, st, (int)nrhs, [&](Workspace& W) {
+    if (F->compute == HODLR_F64) return solve_impl<double>(F, W, trans, (int)nrhs, B, ldb, o, st, stt);
+    return solve_impl<float>(F, W, trans, (int)nrhs, B, ldb, o, st, stt);
+  });
 }
 
-hodlr_status setup(hodlr_factors* F, const hodlr_matrix* A, hodlr_dtype compute) {
+hodlr_status setup(hodlr_factors* F, const hodlr_matrix* A, hodlr_dtype compute, int32_t flags) {
   std::vector<int64_t> off;
   std::vector<int> ranks;
   int m_max = 0;
   hodlr_status s = validate(A, off, ranks, m_max);
   if (s) return s;
+  if (flags & ~HODLR_INPLACE) return HODLR_ERR_ARG;
   if (compute == HODLR_BF16) return HODLR_ERR_UNSUPPORTED;
   if (compute != HODLR_F64 && compute != HODLR_F32) return HODLR_ERR_ARG;
   if (compute == HODLR_F64 && A->dtype != HODLR_F64) return HODLR_ERR_UNSUPPORTED;
+  if (flags & HODLR_INPLACE) {
+    // the factors take the caller's storage: same element type, and every leaf a
+    // whole number of 16-row blocks (no padded block may reach into a neighbour)
+    if ((compute == HODLR_F64) != (A->dtype == HODLR_F64)) return HODLR_ERR_UNSUPPORTED;
+    for (size_t i = 0; i + 1 < off.size(); ++i)
+      if ((off[i + 1] - off[i]) % 16) return HODLR_ERR_UNSUPPORTED;
+  }
+  F->inplace = (flags & HODLR_INPLACE) ? 1 : 0;
   F->n = A->n;
   F->L = A->levels;
   F->nleaf = 1 << F->L;
@@ -802,6 +895,9 @@ hodlr_status setup(hodlr_factors* F, const hodlr_matrix* A, hodlr_dtype compute)
   return HODLR_OK;
 }
 
+hodlr_status grad_impl(hodlr_factors* F, Workspace& Wk, hipStream_t st, int64_t nrhs, const double* X, int64_t ldx,
+                       const double* Lam, int64_t ldl, void* dD, void* dU, void* dV);
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -809,24 +905,27 @@ hodlr_status setup(hodlr_factors* F, const hodlr_matrix* A, hodlr_dtype compute)
 // ---------------------------------------------------------------------------
 extern "C" {
 
-hodlr_status hodlr_factor(const hodlr_matrix* A, hodlr_dtype compute, void* stream, hodlr_factors** out,
-                          hodlr_info* info) {
+hodlr_status hodlr_factor(const hodlr_matrix* A, hodlr_dtype compute, int32_t flags, void* stream,
+                          hodlr_factors** out, hodlr_info* info) {
   if (!out) return HODLR_ERR_ARG;
   *out = nullptr;
   hodlr_factors* F = new hodlr_factors();
-  hodlr_status s = setup(F, A, compute);
+  hodlr_status s = setup(F, A, compute, flags);
   if (s == HODLR_OK) s = allocate_factors(F);
   if (s != HODLR_OK) {
     F->mem.release();
+    if (F->ready) hipEventDestroy(F->ready);
     delete F;
     return s;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   s = dispatch_factor(F, st);
+  if (s == HODLR_OK && hipEventRecord(F->ready, st) != hipSuccess) s = HODLR_ERR_HIP;
   if (s == HODLR_OK) s = verdict(F, st, info);
   if (s < 0) {
     hipStreamSynchronize(st);
     F->mem.release();
+    hipEventDestroy(F->ready);
     delete F;
     return s;
   }
@@ -845,11 +944,23 @@ hodlr_status hodlr_refactor(hodlr_factors* F, const hodlr_matrix* A, void* strea
       A->ldd != F->ldd || A->ldu != F->ldu || A->ldv != F->ldv)
     return HODLR_ERR_ARG;
   std::lock_guard<std::mutex> g(F->mu);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // no call on another stream may still read the old factors: hold every
+  // workspace and make this stream wait for the work each one last recorded
+  std::vector<std::unique_lock<std::mutex>> held;
+  for (auto& kv : F->wsmap) {
+    held.emplace_back(kv.second->mu);
+    if (hipStreamWaitEvent(st, kv.second->done, 0) != hipSuccess) return HODLR_ERR_HIP;
+  }
   F->D = A->D;
   F->U = A->U;
   F->V = A->V;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (F->inplace) {
+    F->lu = const_cast<void*>(F->D);
+    F->Y = const_cast<void*>(F->U);
+  }
   s = dispatch_factor(F, st);
+  if (s == HODLR_OK && hipEventRecord(F->ready, st) != hipSuccess) s = HODLR_ERR_HIP;
   if (s == HODLR_OK) s = verdict(F, st, info);
   return s;
 }
@@ -875,7 +986,7 @@ hodlr_status hodlr_matvec(const hodlr_matrix* A, int32_t trans, int64_t nrhs, co
   if (s) return s;
   if (nrhs == 0) return HODLR_OK;
   if (!X || !Yo || ldx < A->n || ldy < A->n) return HODLR_ERR_ARG;
-  s = setup(&F, A, A->dtype == HODLR_F64 ? HODLR_F64 : HODLR_F32);
+  s = setup(&F, A, A->dtype == HODLR_F64 ? HODLR_F64 : HODLR_F32, 0);
   if (s) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((s = F.mem.alloc(&F.d_off, F.off.size()))) return s;
@@ -898,10 +1009,17 @@ hodlr_status hodlr_grad(const hodlr_factors* Fc, int64_t nrhs, const double* X, 
   hodlr_factors* F = const_cast<hodlr_factors*>(Fc);
   if (!F || nrhs < 1 || nrhs > 65535 || !X || !Lam || ldx < F->n || ldl < F->n || !dD) return HODLR_ERR_ARG;
   if (F->R > 0 && (!dU || !dV)) return HODLR_ERR_ARG;
-  std::lock_guard<std::mutex> g(F->mu);
-  hodlr_status s = ensure_ws(F, (int)nrhs);
-  if (s) return s;
+  if (F->inplace) return HODLR_ERR_ARG;  // the gradients need the original U and V
   hipStream_t st = static_cast<hipStream_t>(stream);
+  return on_stream(F, st, (int)nrhs, [&](Workspace& Wk) { return grad_impl(F, Wk, st, nrhs, X, ldx, Lam, ldl, dD, dU, dV); });
+}
+
+}  // extern "C"
+
+namespace {
+hodlr_status grad_impl(hodlr_factors* F, Workspace& Wk, hipStream_t st, int64_t nrhs, const double* X, int64_t ldx,
+                       const double* Lam, int64_t ldl, void* dD, void* dU, void* dV) {
+  hodlr_status s;
   const int L = F->L;
   const int n = (int)nrhs;
   auto project = [&](const void* Mv, int64_t ldm, const double* Xin, int64_t ldxin, double* tree) -> hodlr_status {
@@ -920,29 +1038,32 @@ hodlr_status hodlr_grad(const hodlr_factors* Fc, int64_t nrhs, const double* X, 
                                       tree + tree_slot(l, 0) * F->R * n));
     return HODLR_OK;
   };
-  if ((s = project(F->V, F->ldv, X, ldx, F->tree))) return s;     // V^T X node sums
-  if ((s = project(F->U, F->ldu, Lam, ldl, F->tree2))) return s;  // U^T Lambda node sums
+  if ((s = project(F->V, F->ldv, X, ldx, Wk.tree))) return s;     // V^T X node sums
+  if ((s = project(F->U, F->ldu, Lam, ldl, Wk.tree2))) return s;  // U^T Lambda node sums
   if (F->storage == HODLR_F64) {
     HL("grad_leaf", (launch_grad_leaf<double>(st, F->nleaf, F->m_max, F->d_off, n, X, ldx, Lam, ldl,
                                               static_cast<double*>(dD), F->ldd)));
     if (F->R > 0 && L > 0) {
-      HL("grad_gen", (launch_grad_gen<double>(st, F->nleaf, L, F->d_off, F->d_rpre, F->R, n, Lam, ldl, F->tree,
+      HL("grad_gen", (launch_grad_gen<double>(st, F->nleaf, L, F->d_off, F->d_rpre, F->R, n, Lam, ldl, Wk.tree,
                                               static_cast<double*>(dU), F->ldu)));
-      HL("grad_gen", (launch_grad_gen<double>(st, F->nleaf, L, F->d_off, F->d_rpre, F->R, n, X, ldx, F->tree2,
+      HL("grad_gen", (launch_grad_gen<double>(st, F->nleaf, L, F->d_off, F->d_rpre, F->R, n, X, ldx, Wk.tree2,
                                               static_cast<double*>(dV), F->ldv)));
     }
   } else {
     HL("grad_leaf", (launch_grad_leaf<float>(st, F->nleaf, F->m_max, F->d_off, n, X, ldx, Lam, ldl,
                                              static_cast<float*>(dD), F->ldd)));
     if (F->R > 0 && L > 0) {
-      HL("grad_gen", (launch_grad_gen<float>(st, F->nleaf, L, F->d_off, F->d_rpre, F->R, n, Lam, ldl, F->tree,
+      HL("grad_gen", (launch_grad_gen<float>(st, F->nleaf, L, F->d_off, F->d_rpre, F->R, n, Lam, ldl, Wk.tree,
                                              static_cast<float*>(dU), F->ldu)));
-      HL("grad_gen", (launch_grad_gen<float>(st, F->nleaf, L, F->d_off, F->d_rpre, F->R, n, X, ldx, F->tree2,
+      HL("grad_gen", (launch_grad_gen<float>(st, F->nleaf, L, F->d_off, F->d_rpre, F->R, n, X, ldx, Wk.tree2,
                                              static_cast<float*>(dV), F->ldv)));
     }
   }
   return HODLR_OK;
 }
+}  // namespace
+
+extern "C" {
 
 hodlr_status hodlr_factors_y(const hodlr_factors* F, double* Yo, int64_t ldy, void* stream) {
   if (!F || (F->R > 0 && (!Yo || ldy < F->n))) return HODLR_ERR_ARG;
@@ -957,13 +1078,28 @@ hodlr_status hodlr_factors_y(const hodlr_factors* F, double* Yo, int64_t ldy, vo
   return HODLR_OK;
 }
 
-size_t hodlr_factor_bytes(const hodlr_factors* F) { return F ? F->mem.bytes + F->ws.bytes : 0; }
+size_t hodlr_factor_bytes(const hodlr_factors* Fc) {
+  if (!Fc) return 0;
+  hodlr_factors* F = const_cast<hodlr_factors*>(Fc);
+  std::lock_guard<std::mutex> g(F->mu);
+  size_t b = F->mem.bytes;
+  for (auto& kv : F->wsmap) b += kv.second->mem.bytes;
+  return b;
+}
 
 void hodlr_destroy(hodlr_factors* F) {
   if (!F) return;
-  hipDeviceSynchronize();
+  // wait only for this factorization's own work: the factorization itself and
+  // the last call on each stream that used it
+  hipEventSynchronize(F->ready);
+  for (auto& kv : F->wsmap) {
+    hipEventSynchronize(kv.second->done);
+    kv.second->mem.release();
+    hipEventDestroy(kv.second->done);
+  }
+  F->wsmap.clear();
   F->mem.release();
-  F->ws.release();
+  hipEventDestroy(F->ready);
   delete F;
 }
 

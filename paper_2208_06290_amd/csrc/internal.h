@@ -58,21 +58,25 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
 // S = storage type of the caller's D/U/V.
 // ---------------------------------------------------------------------------
 
-// leaf LU with partial pivoting; LU blocks col-major ldl x ldl per leaf (ldl % 16 == 0),
-// invl: scratch for the inverted 16 x 16 unit-lower diagonal blocks (ldl/16 x 256 per leaf).
+// leaf LU with partial pivoting; LU blocks col-major ldl x ldl per leaf (ldl % 16 == 0, lul = ldl),
+// or in place (inplace = 1): leaf a's factor in rows [off_a, off_a + m_a) of lu with ld lul
+// (every m_a % 16 == 0; lu may be D itself);
+// invl: the inverted 16 x 16 diagonal blocks of L and U (2 x ldl/16 x 256 per leaf).
 template <typename T, typename S>
 hipError_t launch_leaf_lu(hipStream_t s, int nleaf, int ldl, const int64_t* d_leaf_off, const S* D, int64_t ldd,
-                          T* lu, int32_t* piv, int32_t* perm, T* udinv, T* invl, unsigned long long* info);
+                          T* lu, int64_t lul, int inplace, int32_t* piv, int32_t* perm, T* udinv, T* invl,
+                          unsigned long long* info);
 
 // Leaf triangular solves on column chunks.
 // trans = 0: X(I_a, :) = U_a^{-1} L_a^{-1} P_a^T B(I_a, :)
 // trans = 1: X(I_a, :) = P_a L_a^{-T} U_a^{-T} B(I_a, :)
 // B and X may alias (same type).
 // dinv: per block 2 x (ldl/16) inverted 16 x 16 diagonal blocks ([0]: L, [1]: U) from the factorization.
+// lu, lul, inplace: the leaf factors in either layout of launch_leaf_lu.
 template <typename T, typename S>
 hipError_t launch_leaf_trsm(hipStream_t s, int trans, int nleaf, int ldl, const int64_t* d_leaf_off, const T* lu,
-                            const int32_t* perm, const T* dinv, const S* B, int64_t ldb, T* X, int64_t ldx,
-                            int ncols, int64_t gsb = 256, int64_t gsx = 256);
+                            int64_t lul, int inplace, const int32_t* perm, const T* dinv, const S* B, int64_t ldb,
+                            T* X, int64_t ldx, int ncols, int64_t gsb = 256, int64_t gsx = 256);
 
 // The same solves for nblk equal blocks of m rows (m <= ldl): block g's rows start at X + g * ostride.
 template <typename T>

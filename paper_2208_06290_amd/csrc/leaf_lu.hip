@@ -22,8 +22,10 @@
 // columns in LDS.
 //
 // Output per leaf a (block of ldl x ldl, column-major, ld = ldl; ldl = m_max
-// rounded up to 16):
+// rounded up to 16; or, in place, the leaf's own rows of D with ld = ldd,
+// which needs |I_a| % 16 == 0 so no 16 x 16 block reaches past the leaf):
 //   lu     unit-lower L below the diagonal, U on and above; zero outside m_a x m_a
+//          (the separate layout only)
 //   piv    LAPACK-style interchanges: row j was swapped with piv[j] (0-based, >= j)
 //   perm   composed row order: row i of P^T A is row perm[i] of A
 //   udinv  1 / U_jj (1 outside m_a)
@@ -40,8 +42,9 @@ constexpr int kCW = 32;  // chunk (panel) width
 
 template <typename T, typename S, int CW>
 __global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const int64_t* __restrict__ leaf_off,
-                                                             const S* __restrict__ D, int64_t ldd, T* lu,
-                                                             int32_t* __restrict__ piv, int32_t* __restrict__ perm,
+                                                             const S* D, int64_t ldd, T* lu, int64_t lul,
+                                                             int inplace, int32_t* __restrict__ piv,
+                                                             int32_t* __restrict__ perm,
                                                              T* __restrict__ udinv, T* invl,
                                                              unsigned long long* info) {
   using M = Mfma<T>;
@@ -60,7 +63,7 @@ __global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const i
   const int64_t o = leaf_off[a];
   const int m = (int)(leaf_off[a + 1] - o);
   const int tid0 = threadIdx.x, w0 = __builtin_amdgcn_readfirstlane(tid0 >> 6);
-  T* F = lu + (int64_t)a * ldl * ldl;  // by original row while factoring
+  T* F = lu + (inplace ? o : (int64_t)a * ldl * ldl);  // by original row while factoring (ld lul)
   T* IL = invl + (int64_t)a * 2 * (ldl / 16) * 256;
   int32_t* pv = piv + (int64_t)a * ldl;
   const int nbk = (m + 15) >> 4;
@@ -68,10 +71,10 @@ __global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const i
 
   for (int i = tid0; i < 256; i += kLuThreads) pm[i] = i;
   // zero padding outside m x m (never touched by the factorization)
-  if (m < ldl) {
+  if (m < ldl && !inplace) {
     for (int j = 0; j < ldl; ++j)
       for (int i = tid0; i < ldl; i += kLuThreads)
-        if (i >= m || j >= m) F[i + (int64_t)j * ldl] = T(0);
+        if (i >= m || j >= m) F[i + (int64_t)j * lul] = T(0);
   }
   __syncthreads();
 
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const i
         const int b = min(4 * q + w, nbk - 1);
         const int prow = pm[16 * b + li];
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) av[q][ks] = -F[prow + (int64_t)(16 * k + 4 * ks + lq) * ldl];
+        for (int ks = 0; ks < 4; ++ks) av[q][ks] = -F[prow + (int64_t)(16 * k + 4 * ks + lq) * lul];
       }
       __syncthreads();
 #pragma unroll
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const i
         for (int t = 0; t < 4; ++t) {
           const int row = 16 * (4 * q + w) + M::crow(lq, t);
           const int col = 16 * cb + li;
-          if (row < m && row < c0 && col < cw) F[pm[row] + (int64_t)(c0 + col) * ldl] = acc[q][cb][t];
+          if (row < m && row < c0 && col < cw) F[pm[row] + (int64_t)(c0 + col) * lul] = acc[q][cb][t];
         }
     // 3. panel factorization, one thread per panel row
     const int pr = m - c0;
@@ -235,7 +238,7 @@ __global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const i
     if (own) {
 #pragma unroll
       for (int cc = 0; cc < CW; ++cc)
-        if (cc < cw) F[orig + (int64_t)(c0 + cc) * ldl] = r[cc];
+        if (cc < cw) F[orig + (int64_t)(c0 + cc) * lul] = r[cc];
       if (mypos < CW) {
 #pragma unroll
         for (int cc = 0; cc < CW; ++cc) dblk[mypos * CW + cc] = r[cc];
@@ -300,13 +303,13 @@ __global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const i
 #pragma unroll
       for (int cc = 0; cc < CW; ++cc) {
         const int col = min(CW * g + cc, m - 1);
-        r[cc] = F[min(src, ldl - 1) + (int64_t)col * ldl];
+        r[cc] = F[min(src, m - 1) + (int64_t)col * lul];
       }
       __syncthreads();
       if (moved) {
 #pragma unroll
         for (int cc = 0; cc < CW; ++cc)
-          if (CW * g + cc < m) F[tid + (int64_t)(CW * g + cc) * ldl] = r[cc];
+          if (CW * g + cc < m) F[tid + (int64_t)(CW * g + cc) * lul] = r[cc];
       }
       __syncthreads();
     }
@@ -321,20 +324,24 @@ __global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const i
 
 template <typename T, typename S>
 hipError_t launch_leaf_lu(hipStream_t s, int nleaf, int ldl, const int64_t* d_leaf_off, const S* D, int64_t ldd,
-                          T* lu, int32_t* piv, int32_t* perm, T* udinv, T* invl, unsigned long long* info) {
+                          T* lu, int64_t lul, int inplace, int32_t* piv, int32_t* perm, T* udinv, T* invl,
+                          unsigned long long* info) {
   if (nleaf == 0) return hipSuccess;
   if (ldl % 16 || ldl > 256) return hipErrorInvalidValue;
+  if (inplace ? lul < ldl : lul != ldl) return hipErrorInvalidValue;
   hipLaunchKernelGGL((leaf_lu_kernel<T, S, kCW>), dim3(nleaf), dim3(kLuThreads), 0, s, ldl, d_leaf_off, D, ldd, lu,
-                     piv, perm, udinv, invl, info);
+                     lul, inplace, piv, perm, udinv, invl, info);
   return hipGetLastError();
 }
 
 template hipError_t launch_leaf_lu<double, double>(hipStream_t, int, int, const int64_t*, const double*, int64_t,
-                                                   double*, int32_t*, int32_t*, double*, double*,
+                                                   double*, int64_t, int, int32_t*, int32_t*, double*, double*,
                                                    unsigned long long*);
 template hipError_t launch_leaf_lu<float, double>(hipStream_t, int, int, const int64_t*, const double*, int64_t,
-                                                  float*, int32_t*, int32_t*, float*, float*, unsigned long long*);
+                                                  float*, int64_t, int, int32_t*, int32_t*, float*, float*,
+                                                  unsigned long long*);
 template hipError_t launch_leaf_lu<float, float>(hipStream_t, int, int, const int64_t*, const float*, int64_t,
-                                                 float*, int32_t*, int32_t*, float*, float*, unsigned long long*);
+                                                 float*, int64_t, int, int32_t*, int32_t*, float*, float*,
+                                                 unsigned long long*);
 
 }  // namespace hodlr

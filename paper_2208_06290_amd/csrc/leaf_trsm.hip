@@ -29,8 +29,8 @@ constexpr int kTwLd = 17;  // padded row length of the owner's 16 x 16 turn-arou
 
 template <typename T, typename S, int TRANS, int NW, int NQ, int NCB>
 __global__ __launch_bounds__(64 * NW, NW == 4 ? (NCB <= 2 ? 4 : 2) : (NCB <= 2 ? 2 : 1)) void trsm_kernel(int ldl, const int64_t* __restrict__ leaf_off,
-                                                             int64_t ostride, int mfix, const T* __restrict__ lu,
-                                                             const int32_t* __restrict__ perm,
+                                                             int64_t ostride, int mfix, const T* lu, int64_t lul,
+                                                             int inplace, const int32_t* __restrict__ perm,
                                                              const T* __restrict__ dinv, const S* B, int64_t ldb,
                                                              T* X, int64_t ldx, int ncols, int nchunks, int64_t gsb,
                                                              int64_t gsx) {
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? (NCB <= 2 ? 4 : 2) : (NCB <= 2 ?
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c0 = chunk * kCwT;
   const int nbk = (m + 15) >> 4;
-  const T* F = lu + (int64_t)a * ldl * ldl;
+  const T* F = lu + (inplace ? o : (int64_t)a * ldl * ldl);  // ld lul
   const int32_t* pm = perm + (int64_t)a * ldl;
   const int nbd = ldl >> 4;
   const T* DI = dinv + (int64_t)a * 2 * nbd * 256;  // [0][kb]: inv(L_kk), [1][kb]: inv(U_kk)
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? (NCB <= 2 ? 4 : 2) : (NCB <= 2 ?
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
             const int i = 16 * b + li, j = 16 * k + 4 * ks + lq;
-            av[q2][ks] = -(TRANS ? F[j + (int64_t)i * ldl] : F[i + (int64_t)j * ldl]);
+            av[q2][ks] = -(TRANS ? F[j + (int64_t)i * lul] : F[i + (int64_t)j * lul]);
           }
         }
         // look-ahead: the wave owning the next block updates it first and forms
@@ -204,10 +204,11 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? (NCB <= 2 ? 4 : 2) : (NCB <= 2 ?
 
 template <typename T, typename S>
 static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const int64_t* d_off, int64_t ostride,
-                              int mfix, const T* lu, const int32_t* perm, const T* dinv, const S* B, int64_t ldb, T* X,
-                              int64_t ldx, int ncols, int64_t gsb, int64_t gsx) {
+                              int mfix, const T* lu, int64_t lul, int inplace, const int32_t* perm, const T* dinv,
+                              const S* B, int64_t ldb, T* X, int64_t ldx, int ncols, int64_t gsb, int64_t gsx) {
   if (nblk == 0 || ncols == 0) return hipSuccess;
   if (ldl % 16 || ldl > 256) return hipErrorInvalidValue;
+  if (inplace ? (lul < ldl || !d_off) : lul != ldl) return hipErrorInvalidValue;
   // blocks of at most 64 rows (coupling systems): one 16-row block per wave,
   // chunks of 128 columns for few blocks and of 64 (twice the workgroups per
   // CU) for many; otherwise four blocks per wave and 32 columns
@@ -218,7 +219,7 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
 #define HODLR_TS(TR, NW, NQ, NC)                                                                               \
   hipLaunchKernelGGL((trsm_kernel<T, S, TR, NW, NQ, NC>), dim3((unsigned)grid), dim3(64 * NW), 0, s, ldl, d_off,    \
-                     ostride, mfix, lu, perm, dinv, B, ldb, X, ldx, ncols, nchunks, gsb, gsx)
+                     ostride, mfix, lu, lul, inplace, perm, dinv, B, ldb, X, ldx, ncols, nchunks, gsb, gsx)
   // up to 64 rows: 4 waves, one block each; up to 256 rows: 4 waves with four
   // blocks each for wide right-hand sides, 8 waves with two each for narrow ones
 #define HODLR_TS_W(TR)                         \
@@ -242,26 +243,28 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
 
 template <typename T, typename S>
 hipError_t launch_leaf_trsm(hipStream_t s, int trans, int nleaf, int ldl, const int64_t* d_leaf_off, const T* lu,
-                            const int32_t* perm, const T* dinv, const S* B, int64_t ldb, T* X, int64_t ldx,
-                            int ncols, int64_t gsb, int64_t gsx) {
-  return launch_trsm<T, S>(s, trans, nleaf, ldl, d_leaf_off, 0, 0, lu, perm, dinv, B, ldb, X, ldx, ncols, gsb, gsx);
+                            int64_t lul, int inplace, const int32_t* perm, const T* dinv, const S* B, int64_t ldb,
+                            T* X, int64_t ldx, int ncols, int64_t gsb, int64_t gsx) {
+  return launch_trsm<T, S>(s, trans, nleaf, ldl, d_leaf_off, 0, 0, lu, lul, inplace, perm, dinv, B, ldb, X, ldx, ncols,
+                           gsb, gsx);
 }
 
 template <typename T>
 hipError_t launch_block_trsm(hipStream_t s, int trans, int nblk, int ldl, int m, int64_t ostride, const T* lu,
                              const int32_t* perm, const T* dinv, T* X, int64_t ldx, int ncols) {
-  return launch_trsm<T, T>(s, trans, nblk, ldl, nullptr, ostride, m, lu, perm, dinv, X, ldx, X, ldx, ncols, 256, 256);
+  return launch_trsm<T, T>(s, trans, nblk, ldl, nullptr, ostride, m, lu, ldl, 0, perm, dinv, X, ldx, X, ldx, ncols,
+                           256, 256);
 }
 
 template hipError_t launch_leaf_trsm<double, double>(hipStream_t, int, int, int, const int64_t*, const double*,
-                                                     const int32_t*, const double*, const double*, int64_t,
-                                                     double*, int64_t, int, int64_t, int64_t);
+                                                     int64_t, int, const int32_t*, const double*, const double*,
+                                                     int64_t, double*, int64_t, int, int64_t, int64_t);
 template hipError_t launch_leaf_trsm<float, double>(hipStream_t, int, int, int, const int64_t*, const float*,
-                                                    const int32_t*, const float*, const double*, int64_t,
-                                                    float*, int64_t, int, int64_t, int64_t);
+                                                    int64_t, int, const int32_t*, const float*, const double*,
+                                                    int64_t, float*, int64_t, int, int64_t, int64_t);
 template hipError_t launch_leaf_trsm<float, float>(hipStream_t, int, int, int, const int64_t*, const float*,
-                                                   const int32_t*, const float*, const float*, int64_t, float*,
-                                                   int64_t, int, int64_t, int64_t);
+                                                   int64_t, int, const int32_t*, const float*, const float*,
+                                                   int64_t, float*, int64_t, int, int64_t, int64_t);
 template hipError_t launch_block_trsm<double>(hipStream_t, int, int, int, int, int64_t, const double*,
                                               const int32_t*, const double*, double*, int64_t, int);
 template hipError_t launch_block_trsm<float>(hipStream_t, int, int, int, int, int64_t, const float*, const int32_t*,
