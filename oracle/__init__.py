@@ -13,6 +13,7 @@ from .hodlr_oracle import (  # noqa: F401
     factor,
     solve,
     y_big,
+    slogdet,
     transpose,
     solve_adjoint,
     matvec,

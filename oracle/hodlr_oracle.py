@@ -191,6 +191,44 @@ def y_big(F: dict) -> np.ndarray:
     return Y
 
 
+def _lu_slogdet(lu_piv):
+    """(sign, log|det|) of a matrix from its LAPACK LU: the product of U's
+    diagonal, with one sign change per row interchange."""
+    lu, piv = lu_piv
+    d = np.diag(lu)
+    swaps = int(np.sum(piv != np.arange(len(piv))))
+    sign = (-1.0) ** swaps * float(np.prod(np.sign(d)))
+    return sign, float(np.sum(np.log(np.abs(d))))
+
+
+def slogdet(F: dict):
+    """(sign, log|det A|) from the factorization (the appendix's product form
+    A = A^(L+1) A^(L) ... A^(1): leaf blocks, then per level block-diagonal
+    2x2 factors [[I, Y_a V_b^T], [Y_b V_a^T, I]]).  By Sylvester's determinant
+    theorem each 2x2 factor has the determinant of [[I, T_b], [T_a, I]] with
+    T = V^T Y, which is K = [[T_a, I], [I, T_b]] with its two r-row blocks
+    swapped: det = (-1)^r det K."""
+    sign, logabs = 1.0, 0.0
+
+    def walk(node):
+        nonlocal sign, logabs
+        if node["leaf"]:
+            sg, la = _lu_slogdet(node["lu"])
+            sign *= sg
+            logabs += la
+            return
+        walk(node["a"])
+        walk(node["b"])
+        if node["Klu"] is not None:
+            r = node["Ya"].shape[1]
+            sg, la = _lu_slogdet(node["Klu"])
+            sign *= sg * (-1.0) ** r
+            logabs += la
+
+    walk(F)
+    return sign, logabs
+
+
 # ---------------------------------------------------------------------------
 # transpose, adjoint, matvec, gradients
 # ---------------------------------------------------------------------------

@@ -199,6 +199,40 @@ def test_assembly_matches_the_uncompressed_operators():
     assert _rel(O.assemble_dense(H), K) < 1e-3
 
 
+# ---- determinant -------------------------------------------------------------------
+
+@pytest.mark.parametrize("c", CASES + [dict(n=384, leaf=None, rank=[3, 5, 1], L=3)])
+def test_slogdet_matches_dense(c):
+    """log|det A| and its sign from the factors equal LAPACK's on the
+    assembled matrix; odd ranks make the (-1)^r of each 2x2 factor matter, and
+    negative shifts give negative determinants."""
+    for seed, shift in ((0, 4.0), (1, -4.0)):
+        H = _case(c, seed=seed) if shift > 0 else _mk(c["n"], c.get("leaf"), c["rank"], seed=seed, shift=shift,
+                                                      offsets=None if c.get("leaf") is not None else
+                                                      _nonuniform_offsets(c["n"], c["L"], seed))
+        sg, la = O.slogdet(O.factor(H))
+        sd, ld = np.linalg.slogdet(O.assemble_dense(H))
+        assert sg == sd and la == pytest.approx(ld, rel=1e-12, abs=1e-9), (sg, sd, la, ld)
+
+
+@pytest.mark.parametrize("mistake", ["no_sign_r", "no_K"])
+def test_planted_slogdet_mistakes_fail(monkeypatch, mistake):
+    """The dense pin catches a dropped (-1)^r per 2x2 factor and a dropped
+    coupling-matrix determinant (strong coupling: small diagonal shift)."""
+    H = _mk(512, 64, [3, 5, 1], seed=2, shift=0.25)
+    sd, ld = np.linalg.slogdet(O.assemble_dense(H))
+    if mistake == "no_sign_r":
+        sg, la = O.slogdet(O.factor(H))
+        # without the factor the sign flips once per node whose rank is odd
+        nodes_odd = sum(1 << (lv - 1) for lv, r in enumerate(H.ranks, start=1) if r % 2)
+        assert nodes_odd % 2 == 1 and sg * (-1.0) ** nodes_odd != sd
+    else:
+        good = OH._lu_slogdet
+        monkeypatch.setattr(OH, "_lu_slogdet", lambda lu_piv: good(lu_piv) if lu_piv[0].shape[0] == 64 else (1.0, 0.0))
+        sg, la = O.slogdet(O.factor(H))
+        assert la != pytest.approx(ld, rel=1e-12, abs=1e-9)  # the pin's tolerance
+
+
 # ---- adjoint and gradients --------------------------------------------------------
 
 def test_adjoint_dot_test_and_dense():
