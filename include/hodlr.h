@@ -143,7 +143,14 @@ typedef struct {
  * K_g = [[V_a^T Y_a, I], [I, V_b^T Y_b]] (eq. "e:k") and the update of
  * Y_big(:, 1:R_l) (eqs. "e:node1", "e:node2").
  *   A        the matrix (see hodlr_matrix)
- *   compute  HODLR_F64 (requires dtype F64), HODLR_F32 or HODLR_BF16
+ *   compute  HODLR_F64 (requires dtype F64), HODLR_F32 or HODLR_BF16.  F32
+ *            and BF16 keep FP32 factors (leaf LU, Y_big, K); BF16 rounds the
+ *            operands of the matrix-core products to bfloat16 with FP32
+ *            accumulation (the leaf LU's trailing updates, the leaf solve on
+ *            U_big and the coupling products and updates V^T Y, Y W), while
+ *            the pivot searches, the panels and the coupling matrices K stay
+ *            FP32.  Solves with F32/BF16 factors run in FP32; opts->refine
+ *            recovers FP64 accuracy.
  *   flags    0 or HODLR_INPLACE (other bits: HODLR_ERR_ARG)
  *   F        out: new factorization object (NULL on negative status)
  * Returns HODLR_ERR_SINGULAR (factors kept but unusable; *info filled if

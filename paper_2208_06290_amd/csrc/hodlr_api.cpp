@@ -481,8 +481,10 @@ hodlr_status prod_segments(hodlr_factors* F, hipStream_t st, int q, int p, int64
   return HODLR_OK;
 }
 
+// bf = 1: the leaf LU updates, the leaf solve and the level-pass products take
+// bfloat16 operands (FP32 factors, accumulation, panels and K)
 template <typename T, typename S>
-hodlr_status run_factor(hodlr_factors* F, hipStream_t st) {
+hodlr_status run_factor(hodlr_factors* F, hipStream_t st, int bf) {
   const int L = F->L;
   const int64_t N = F->n;
   T* Y = tp<T>(F->Y);
@@ -491,16 +493,16 @@ hodlr_status run_factor(hodlr_factors* F, hipStream_t st) {
   const S* V = static_cast<const S*>(F->V);
   if (hipMemsetAsync(F->d_info, 0xFF, 2 * sizeof(unsigned long long), st) != hipSuccess) return HODLR_ERR_HIP;
   HL("leaf_lu", (launch_leaf_lu<T, S>(st, F->nleaf, F->ldl, F->d_off, D, F->ldd, tp<T>(F->lu), F->lul, F->inplace,
-                                      F->piv, F->perm, tp<T>(F->udinv), tp<T>(F->invl), F->d_info)));
+                                      F->piv, F->perm, tp<T>(F->udinv), tp<T>(F->invl), F->d_info, bf)));
   if (F->R > 0)
     HL("leaf_trsm", (launch_leaf_trsm<T, S>(st, 0, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->lul, F->inplace,
-                                            F->perm, tp<T>(F->invl), U, F->ldu, Y, F->ldy, F->R, 256, F->gsy)));
+                                            F->perm, tp<T>(F->invl), U, F->ldu, Y, F->ldy, F->R, 256, F->gsy, bf)));
   if (L > 0) {
     // products V^T Y for the children of level L-1 (the leaves)
     HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[L], F->d_tiles[L], F->tiles_aligned[L], Y, F->ldy, F->R,
                                                  (const T*)nullptr, F->ldy, 0, (const T*)nullptr, 0, 0, 0,
                                                  V + (int64_t)F->Rp[L - 1] * F->ldv, F->ldv, F->ranks[L - 1],
-                                                 tp<T>(F->P), GroupStrides{F->gsy, F->gsy, 256})));
+                                                 tp<T>(F->P), GroupStrides{F->gsy, F->gsy, 256}, bf)));
     for (int p = L - 1; p >= 0; --p) {
       const int q = p + 1;
       const int r = F->ranks[q - 1];
@@ -524,13 +526,13 @@ hodlr_status run_factor(hodlr_factors* F, hipStream_t st) {
            (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], F->tiles_aligned[q], Y, F->ldy, Rp,
                                        Y + (int64_t)Rp * F->ldy, F->ldy, r, tp<T>(F->W), 2 * r, (int64_t)2 * r * Rp, 0,
                                        V + (int64_t)F->Rp[p - 1] * F->ldv, F->ldv, F->ranks[p - 1], tp<T>(F->P),
-                                       GroupStrides{F->gsy, F->gsy, 256})));
+                                       GroupStrides{F->gsy, F->gsy, 256}, bf)));
       } else if (p > 0) {
         // rank-0 children: no update; products for level p still needed
         HL("level_pass", (launch_level_pass<T, T, S>(st, F->ntiles[q], F->d_tiles[q], F->tiles_aligned[q], Y, F->ldy,
                                                      Rp, (const T*)nullptr, F->ldy, 0, (const T*)nullptr, 0, 0, 0,
                                                      V + (int64_t)F->Rp[p - 1] * F->ldv, F->ldv, F->ranks[p - 1],
-                                                     tp<T>(F->P), GroupStrides{F->gsy, F->gsy, 256})));
+                                                     tp<T>(F->P), GroupStrides{F->gsy, F->gsy, 256}, bf)));
       }
     }
   }
@@ -566,9 +568,10 @@ hodlr_status verdict(hodlr_factors* F, hipStream_t st, hodlr_info* info) {
 }
 
 hodlr_status dispatch_factor(hodlr_factors* F, hipStream_t st) {
-  if (F->compute == HODLR_F64) return run_factor<double, double>(F, st);
-  if (F->storage == HODLR_F64) return run_factor<float, double>(F, st);
-  return run_factor<float, float>(F, st);
+  if (F->compute == HODLR_F64) return run_factor<double, double>(F, st, 0);
+  const int bf = F->compute == HODLR_BF16 ? 1 : 0;
+  if (F->storage == HODLR_F64) return run_factor<float, double>(F, st, bf);
+  return run_factor<float, float>(F, st, bf);
 }
 
 // ---- solve-side workspace --------------------------------------------------
@@ -862,8 +865,7 @@ hodlr_status setup(hodlr_factors* F, const hodlr_matrix* A, hodlr_dtype compute,
   hodlr_status s = validate(A, off, ranks, m_max);
   if (s) return s;
   if (flags & ~HODLR_INPLACE) return HODLR_ERR_ARG;
-  if (compute == HODLR_BF16) return HODLR_ERR_UNSUPPORTED;
-  if (compute != HODLR_F64 && compute != HODLR_F32) return HODLR_ERR_ARG;
+  if (compute != HODLR_F64 && compute != HODLR_F32 && compute != HODLR_BF16) return HODLR_ERR_ARG;
   if (compute == HODLR_F64 && A->dtype != HODLR_F64) return HODLR_ERR_UNSUPPORTED;
   if (flags & HODLR_INPLACE) {
     // the factors take the caller's storage: same element type, and every leaf a

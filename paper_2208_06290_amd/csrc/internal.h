@@ -62,10 +62,12 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
 // or in place (inplace = 1): leaf a's factor in rows [off_a, off_a + m_a) of lu with ld lul
 // (every m_a % 16 == 0; lu may be D itself);
 // invl: the inverted 16 x 16 diagonal blocks of L and U (2 x ldl/16 x 256 per leaf).
+// bf = 1 (T = float): the trailing updates of the left-looking sweep take
+// bfloat16 operands with FP32 accumulation; pivot search and panel stay FP32.
 template <typename T, typename S>
 hipError_t launch_leaf_lu(hipStream_t s, int nleaf, int ldl, const int64_t* d_leaf_off, const S* D, int64_t ldd,
                           T* lu, int64_t lul, int inplace, int32_t* piv, int32_t* perm, T* udinv, T* invl,
-                          unsigned long long* info);
+                          unsigned long long* info, int bf = 0);
 
 // Leaf triangular solves on column chunks.
 // trans = 0: X(I_a, :) = U_a^{-1} L_a^{-1} P_a^T B(I_a, :)
@@ -73,10 +75,12 @@ hipError_t launch_leaf_lu(hipStream_t s, int nleaf, int ldl, const int64_t* d_le
 // B and X may alias (same type).
 // dinv: per block 2 x (ldl/16) inverted 16 x 16 diagonal blocks ([0]: L, [1]: U) from the factorization.
 // lu, lul, inplace: the leaf factors in either layout of launch_leaf_lu.
+// bf = 1 (T = float, trans = 0): the block products take bfloat16 operands with
+// FP32 accumulation (the leaf solve of a BF16 factorization).
 template <typename T, typename S>
 hipError_t launch_leaf_trsm(hipStream_t s, int trans, int nleaf, int ldl, const int64_t* d_leaf_off, const T* lu,
                             int64_t lul, int inplace, const int32_t* perm, const T* dinv, const S* B, int64_t ldb,
-                            T* X, int64_t ldx, int ncols, int64_t gsb = 256, int64_t gsx = 256);
+                            T* X, int64_t ldx, int ncols, int64_t gsb = 256, int64_t gsx = 256, int bf = 0);
 
 // The same solves for nblk equal blocks of m rows (m <= ldl): block g's rows start at X + g * ostride.
 template <typename T>
@@ -95,6 +99,9 @@ hipError_t launch_block_trsm(hipStream_t s, int trans, int nblk, int ldl, int m,
 // column-major layout; gs = 256 * ncols with ld = 256 is the row-group blocked
 // layout (each 256-row group of all columns contiguous), valid when no tile
 // crosses a 256-row boundary.
+// bf = 1 (4-byte TZ): the products of the fast kernel take bfloat16 operands
+// with FP32 accumulation (the coupling GEMMs of a BF16 factorization); tiles
+// that need the general kernel are computed in FP32.
 struct GroupStrides {
   int64_t z = 256, a = 256, b = 256;
 };
@@ -104,7 +111,7 @@ template <typename TZ, typename SA, typename SB>
 hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int tiles_aligned, TZ* Z, int64_t ldz, int nz,
                              const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld,
                              int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
-                             GroupStrides gs = GroupStrides());
+                             GroupStrides gs = GroupStrides(), int bf = 0);
 
 // Segment sums of tile partials: out[s] = sum of tiles [desc[s].x, desc[s].x + desc[s].y),
 // maxy = max over s of desc[s].y (<= kSegTiles).

@@ -40,7 +40,7 @@ namespace hodlr {
 constexpr int kLuThreads = 256;
 constexpr int kCW = 32;  // chunk (panel) width
 
-template <typename T, typename S, int CW>
+template <typename T, typename S, int CW, bool BF>
 __global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const int64_t* __restrict__ leaf_off,
                                                              const S* D, int64_t ldd, T* lu, int64_t lul,
                                                              int inplace, int32_t* __restrict__ piv,
@@ -115,9 +115,13 @@ __global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const i
           if (4 * q + w == k) {
 #pragma unroll
             for (int cb = 0; cb < CW / 16; ++cb) {
-              V nv = vzero<V>();
+              T lv[4], bv[4];
 #pragma unroll
-              for (int t = 0; t < 4; ++t) nv = M::mma(ILs[k * 256 + li * 16 + M::crow(lq, t)], acc[q][cb][t], nv);
+              for (int t = 0; t < 4; ++t) {
+                lv[t] = ILs[k * 256 + li * 16 + M::crow(lq, t)];
+                bv[t] = acc[q][cb][t];
+              }
+              const V nv = Mma16<T, BF>::mma(lv, bv, vzero<V>());
               acc[q][cb] = nv;
 #pragma unroll
               for (int t = 0; t < 4; ++t) xb[M::crow(lq, t) * CW + 16 * cb + li] = nv[t];
@@ -139,11 +143,21 @@ __global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const i
       for (int q = 0; q < 4; ++q) {
         const int b = 4 * q + w;
         if (b > k && b < nbk) {  // uniform
+          if constexpr (BF) {
 #pragma unroll
-          for (int ks = 0; ks < 4; ++ks)
+            for (int cb = 0; cb < CW / 16; ++cb) {
+              T xv[4];
 #pragma unroll
-            for (int cb = 0; cb < CW / 16; ++cb)
-              acc[q][cb] = M::mma(av[q][ks], xb[(4 * ks + lq) * CW + 16 * cb + li], acc[q][cb]);
+              for (int ks = 0; ks < 4; ++ks) xv[ks] = xb[(4 * ks + lq) * CW + 16 * cb + li];
+              acc[q][cb] = Mma16<T, true>::mma(av[q], xv, acc[q][cb]);
+            }
+          } else {
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+              for (int cb = 0; cb < CW / 16; ++cb)
+                acc[q][cb] = M::mma(av[q][ks], xb[(4 * ks + lq) * CW + 16 * cb + li], acc[q][cb]);
+          }
         }
       }
     }
@@ -325,23 +339,30 @@ __global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const i
 template <typename T, typename S>
 hipError_t launch_leaf_lu(hipStream_t s, int nleaf, int ldl, const int64_t* d_leaf_off, const S* D, int64_t ldd,
                           T* lu, int64_t lul, int inplace, int32_t* piv, int32_t* perm, T* udinv, T* invl,
-                          unsigned long long* info) {
+                          unsigned long long* info, int bf) {
   if (nleaf == 0) return hipSuccess;
   if (ldl % 16 || ldl > 256) return hipErrorInvalidValue;
   if (inplace ? lul < ldl : lul != ldl) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((leaf_lu_kernel<T, S, kCW>), dim3(nleaf), dim3(kLuThreads), 0, s, ldl, d_leaf_off, D, ldd, lu,
-                     lul, inplace, piv, perm, udinv, invl, info);
+  if constexpr (sizeof(T) == 4) {
+    if (bf) {
+      hipLaunchKernelGGL((leaf_lu_kernel<T, S, kCW, true>), dim3(nleaf), dim3(kLuThreads), 0, s, ldl, d_leaf_off, D,
+                         ldd, lu, lul, inplace, piv, perm, udinv, invl, info);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((leaf_lu_kernel<T, S, kCW, false>), dim3(nleaf), dim3(kLuThreads), 0, s, ldl, d_leaf_off, D, ldd,
+                     lu, lul, inplace, piv, perm, udinv, invl, info);
   return hipGetLastError();
 }
 
 template hipError_t launch_leaf_lu<double, double>(hipStream_t, int, int, const int64_t*, const double*, int64_t,
                                                    double*, int64_t, int, int32_t*, int32_t*, double*, double*,
-                                                   unsigned long long*);
+                                                   unsigned long long*, int);
 template hipError_t launch_leaf_lu<float, double>(hipStream_t, int, int, const int64_t*, const double*, int64_t,
                                                   float*, int64_t, int, int32_t*, int32_t*, float*, float*,
-                                                  unsigned long long*);
+                                                  unsigned long long*, int);
 template hipError_t launch_leaf_lu<float, float>(hipStream_t, int, int, const int64_t*, const float*, int64_t,
                                                  float*, int64_t, int, int32_t*, int32_t*, float*, float*,
-                                                 unsigned long long*);
+                                                 unsigned long long*, int);
 
 }  // namespace hodlr

@@ -27,7 +27,7 @@ namespace hodlr {
 
 constexpr int kTwLd = 17;  // padded row length of the owner's 16 x 16 turn-around buffer
 
-template <typename T, typename S, int TRANS, int NW, int NQ, int NCB>
+template <typename T, typename S, int TRANS, int NW, int NQ, int NCB, bool BF>
 __global__ __launch_bounds__(64 * NW, NW == 4 ? (NCB <= 2 ? 4 : 2) : (NCB <= 2 ? 2 : 1)) void trsm_kernel(int ldl, const int64_t* __restrict__ leaf_off,
                                                              int64_t ostride, int mfix, const T* lu, int64_t lul,
                                                              int inplace, const int32_t* __restrict__ perm,
@@ -109,9 +109,10 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? (NCB <= 2 ? 4 : 2) : (NCB <= 2 ?
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) twv[li * kTwLd + M::crow(lq, t)] = acc[q][cb][t];
-      V nv = vzero<V>();
+      T tv[4];
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) nv = M::mma(twv[(4 * ks + lq) * kTwLd + li], iv[ks], nv);
+      for (int ks = 0; ks < 4; ++ks) tv[ks] = twv[(4 * ks + lq) * kTwLd + li];
+      const V nv = Mma16<T, BF>::mma(tv, iv, vzero<V>());
       acc[q][cb] = nv;
 #pragma unroll
       for (int t = 0; t < 4; ++t) xb[li * kCwT + 16 * cb + M::crow(lq, t)] = nv[t];
@@ -119,11 +120,21 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? (NCB <= 2 ? 4 : 2) : (NCB <= 2 ?
   };
   // B_b^T -= X_k^T M_bk^T on accumulator block q2
   auto update = [&](int q2, const T (&av)[NQ][4], const T* xb) {
+    if constexpr (BF) {
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
+      for (int cb = 0; cb < NCB; ++cb) {
+        T xv[4];
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
-        acc[q2][cb] = M::mma(xb[(4 * ks + lq) * kCwT + 16 * cb + li], av[q2][ks], acc[q2][cb]);
+        for (int ks = 0; ks < 4; ++ks) xv[ks] = xb[(4 * ks + lq) * kCwT + 16 * cb + li];
+        acc[q2][cb] = Mma16<T, true>::mma(xv, av[q2], acc[q2][cb]);
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[q2][cb] = M::mma(xb[(4 * ks + lq) * kCwT + 16 * cb + li], av[q2][ks], acc[q2][cb]);
+    }
   };
 
   // The steps are unrolled so that every block index is a compile-time
@@ -205,7 +216,8 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? (NCB <= 2 ? 4 : 2) : (NCB <= 2 ?
 template <typename T, typename S>
 static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const int64_t* d_off, int64_t ostride,
                               int mfix, const T* lu, int64_t lul, int inplace, const int32_t* perm, const T* dinv,
-                              const S* B, int64_t ldb, T* X, int64_t ldx, int ncols, int64_t gsb, int64_t gsx) {
+                              const S* B, int64_t ldb, T* X, int64_t ldx, int ncols, int64_t gsb, int64_t gsx,
+                              int bf) {
   if (nblk == 0 || ncols == 0) return hipSuccess;
   if (ldl % 16 || ldl > 256) return hipErrorInvalidValue;
   if (inplace ? (lul < ldl || !d_off) : lul != ldl) return hipErrorInvalidValue;
@@ -217,9 +229,10 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
   const int nchunks = (ncols + cw - 1) / cw;
   const int64_t grid = (int64_t)nblk * nchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-#define HODLR_TS(TR, NW, NQ, NC)                                                                               \
-  hipLaunchKernelGGL((trsm_kernel<T, S, TR, NW, NQ, NC>), dim3((unsigned)grid), dim3(64 * NW), 0, s, ldl, d_off,    \
+#define HODLR_TS_B(TR, NW, NQ, NC, BFV)                                                                             \
+  hipLaunchKernelGGL((trsm_kernel<T, S, TR, NW, NQ, NC, BFV>), dim3((unsigned)grid), dim3(64 * NW), 0, s, ldl, d_off, \
                      ostride, mfix, lu, lul, inplace, perm, dinv, B, ldb, X, ldx, ncols, nchunks, gsb, gsx)
+#define HODLR_TS(TR, NW, NQ, NC) HODLR_TS_B(TR, NW, NQ, NC, false)
   // up to 64 rows: 4 waves, one block each; up to 256 rows: 4 waves with four
   // blocks each for wide right-hand sides, 8 waves with two each for narrow ones
 #define HODLR_TS_W(TR)                         \
@@ -231,40 +244,52 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
     if (cw == 32) HODLR_TS(TR, 4, 4, 2);       \
     else HODLR_TS(TR, 8, 2, 1);                \
   }
-  if (trans) {
+  // bfloat16 operands (FP32 factors and accumulation): the leaf solve of a
+  // BF16 factorization
+  bool done = false;
+  if constexpr (sizeof(T) == 4) {
+    if (bf && !trans && nq == 4) {
+      if (cw == 32) HODLR_TS_B(0, 4, 4, 2, true);
+      else HODLR_TS_B(0, 8, 2, 1, true);
+      done = true;
+    }
+  }
+  if (done) {
+  } else if (trans) {
     HODLR_TS_W(1)
   } else {
     HODLR_TS_W(0)
   }
 #undef HODLR_TS_W
 #undef HODLR_TS
+#undef HODLR_TS_B
   return hipGetLastError();
 }
 
 template <typename T, typename S>
 hipError_t launch_leaf_trsm(hipStream_t s, int trans, int nleaf, int ldl, const int64_t* d_leaf_off, const T* lu,
                             int64_t lul, int inplace, const int32_t* perm, const T* dinv, const S* B, int64_t ldb,
-                            T* X, int64_t ldx, int ncols, int64_t gsb, int64_t gsx) {
+                            T* X, int64_t ldx, int ncols, int64_t gsb, int64_t gsx, int bf) {
   return launch_trsm<T, S>(s, trans, nleaf, ldl, d_leaf_off, 0, 0, lu, lul, inplace, perm, dinv, B, ldb, X, ldx, ncols,
-                           gsb, gsx);
+                           gsb, gsx, bf);
 }
 
 template <typename T>
 hipError_t launch_block_trsm(hipStream_t s, int trans, int nblk, int ldl, int m, int64_t ostride, const T* lu,
                              const int32_t* perm, const T* dinv, T* X, int64_t ldx, int ncols) {
   return launch_trsm<T, T>(s, trans, nblk, ldl, nullptr, ostride, m, lu, ldl, 0, perm, dinv, X, ldx, X, ldx, ncols,
-                           256, 256);
+                           256, 256, 0);
 }
 
 template hipError_t launch_leaf_trsm<double, double>(hipStream_t, int, int, int, const int64_t*, const double*,
                                                      int64_t, int, const int32_t*, const double*, const double*,
-                                                     int64_t, double*, int64_t, int, int64_t, int64_t);
+                                                     int64_t, double*, int64_t, int, int64_t, int64_t, int);
 template hipError_t launch_leaf_trsm<float, double>(hipStream_t, int, int, int, const int64_t*, const float*,
                                                     int64_t, int, const int32_t*, const float*, const double*,
-                                                    int64_t, float*, int64_t, int, int64_t, int64_t);
+                                                    int64_t, float*, int64_t, int, int64_t, int64_t, int);
 template hipError_t launch_leaf_trsm<float, float>(hipStream_t, int, int, int, const int64_t*, const float*,
                                                    int64_t, int, const int32_t*, const float*, const float*,
-                                                   int64_t, float*, int64_t, int, int64_t, int64_t);
+                                                   int64_t, float*, int64_t, int, int64_t, int64_t, int);
 template hipError_t launch_block_trsm<double>(hipStream_t, int, int, int, int, int64_t, const double*,
                                               const int32_t*, const double*, double*, int64_t, int);
 template hipError_t launch_block_trsm<float>(hipStream_t, int, int, int, int, int64_t, const float*, const int32_t*,

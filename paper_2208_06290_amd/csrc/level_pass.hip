@@ -17,6 +17,7 @@
 #include "mfma.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace hodlr {
 
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
 // over rows does not depend on their order).
 constexpr int kZtLd = 17;  // padded row length of the per-wave 16 x 16 turn-around buffer
 
-template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE, int RP>
+template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE, int RP, bool BF>
 __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level_pass_fast_kernel(
     const Tile* __restrict__ tiles, int zchunks, int c_base, int bchunks, TZ* Z, int64_t ldz, int nz, const SA* __restrict__ A1,
     int64_t lda, const TZ* __restrict__ W, int64_t w_ld, int64_t w_pstride, int node_shift,
@@ -305,11 +306,27 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
 
   // update of one 16-row MFMA block, and its contribution to the product
   auto update = [&](V (&acc)[NCB], const TZ (&acur)[NKS > 0 ? NKS : 1]) {
+    if constexpr (BF) {
+      // groups of four K-steps as one bfloat16 MFMA (NKS is a multiple of 4)
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks)
+      for (int g = 0; g < NKS / 4; ++g)
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
-        acc[cb] = M::mma(Ws[(4 * ks + lq) * kCw + 16 * cb + li], acur[ks], acc[cb]);
+        for (int cb = 0; cb < NCB; ++cb) {
+          TZ wv[4], av4[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            wv[j] = Ws[(4 * (4 * g + j) + lq) * kCw + 16 * cb + li];
+            av4[j] = acur[4 * g + j];
+          }
+          acc[cb] = Mma16<TZ, true>::mma(wv, av4, acc[cb]);
+        }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[cb] = M::mma(Ws[(4 * ks + lq) * kCw + 16 * cb + li], acur[ks], acc[cb]);
+    }
   };
   auto stage_b = [&](const TZ (&bcur)[MB > 0 ? 4 * MB : 1]) {
 #pragma unroll
@@ -327,11 +344,24 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) zt[li * kZtLd + M::crow(lq, t)] = acc[cb][t];
+      if constexpr (BF) {
+        TZ zv4[4];
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const TZ zv = zt[(4 * kk + lq) * kZtLd + li];
+        for (int kk = 0; kk < 4; ++kk) zv4[kk] = zt[(4 * kk + lq) * kZtLd + li];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) pacc[mb][cb] = M::mma(bv[kk][mb], zv, pacc[mb][cb]);
+        for (int mb = 0; mb < MB; ++mb) {
+          TZ b4[4];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) b4[kk] = bv[kk][mb];
+          pacc[mb][cb] = Mma16<TZ, true>::mma(b4, zv4, pacc[mb][cb]);
+        }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const TZ zv = zt[(4 * kk + lq) * kZtLd + li];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) pacc[mb][cb] = M::mma(bv[kk][mb], zv, pacc[mb][cb]);
+        }
       }
     }
   };
@@ -405,7 +435,7 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
   }
 }
 
-template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE, int RP>
+template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE, int RP, bool BF>
 static hipError_t launch_part(hipStream_t s, int ntiles, int zchunks, int c_base, int nz, int bchunks,
                               const Tile* tiles, TZ* Z, int64_t ldz, const SA* A1, int64_t lda, const TZ* W,
                               int64_t w_ld, int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
@@ -417,7 +447,7 @@ static hipError_t launch_part(hipStream_t s, int ntiles, int zchunks, int c_base
   const size_t smem = smem_main > smem_red ? smem_main : smem_red;
   const int64_t grid = (int64_t)ntiles * zchunks * bchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  auto k = level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, MODE, RP>;
+  auto k = level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, MODE, RP, BF>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kLpThreads), smem, s, tiles, zchunks, c_base, bchunks, Z, ldz, nz,
@@ -428,34 +458,34 @@ static hipError_t launch_part(hipStream_t s, int ntiles, int zchunks, int c_base
 // Columns of Z in up to three launches: chunks of 64, then the whole 16-column
 // blocks that are left as one narrower chunk, then a last partial block
 // (per-lane column test).  Every launch computes only columns that exist.
-template <typename TZ, typename SA, typename SB, int MB, int NKS, int RP>
+template <typename TZ, typename SA, typename SB, int MB, int NKS, int RP, bool BF>
 static hipError_t launch_fast(hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z, int64_t ldz,
                               const SA* A1, int64_t lda, const TZ* W, int64_t w_ld, int64_t w_pstride,
                               int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P, GroupStrides gs) {
   const int n64 = nz / 64, nb = (nz % 64) / 16, tail = nz % 16;
-  hipError_t e = launch_part<TZ, SA, SB, MB, NKS, 4, 0, RP>(s, ntiles, n64, 0, nz, bchunks, tiles, Z, ldz, A1, lda, W,
+  hipError_t e = launch_part<TZ, SA, SB, MB, NKS, 4, 0, RP, BF>(s, ntiles, n64, 0, nz, bchunks, tiles, Z, ldz, A1, lda, W,
                                                          w_ld, w_pstride, node_shift, B1, ldb, kb, P, gs);
   if (e != hipSuccess) return e;
   const int cb = 64 * n64;
 #define HODLR_LPB(NCBV)                                                                                          \
-  e = launch_part<TZ, SA, SB, MB, NKS, NCBV, 0, RP>(s, ntiles, 1, cb, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,  \
+  e = launch_part<TZ, SA, SB, MB, NKS, NCBV, 0, RP, BF>(s, ntiles, 1, cb, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,  \
                                                  w_pstride, node_shift, B1, ldb, kb, P, gs)
   if (nb == 1) HODLR_LPB(1);
   else if (nb == 2) HODLR_LPB(2);
   else if (nb == 3) HODLR_LPB(3);
 #undef HODLR_LPB
   if (e != hipSuccess) return e;
-  return launch_part<TZ, SA, SB, MB, NKS, 1, 2, RP>(s, ntiles, tail ? 1 : 0, cb + 16 * nb, nz, bchunks, tiles, Z, ldz, A1,
+  return launch_part<TZ, SA, SB, MB, NKS, 1, 2, RP, BF>(s, ntiles, tail ? 1 : 0, cb + 16 * nb, nz, bchunks, tiles, Z, ldz, A1,
                                                 lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P, gs);
 }
 
-template <typename TZ, typename SA, typename SB, int MB, int RP>
+template <typename TZ, typename SA, typename SB, int MB, int RP, bool BF>
 static hipError_t launch_fast_nks(int nks, hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z,
                                   int64_t ldz, const SA* A1, int64_t lda, const TZ* W, int64_t w_ld,
                                   int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
                                   GroupStrides gs) {
 #define HODLR_LPF(NKSV)                                                                                       \
-  return launch_fast<TZ, SA, SB, MB, NKSV, RP>(s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld, w_pstride,      \
+  return launch_fast<TZ, SA, SB, MB, NKSV, RP, BF>(s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld, w_pstride,      \
                                                  node_shift, B1, ldb, kb, P, gs)
   switch (nks) {
     case 0: HODLR_LPF(0);
@@ -467,14 +497,14 @@ static hipError_t launch_fast_nks(int nks, hipStream_t s, int ntiles, int nz, in
 #undef HODLR_LPF
 }
 
-template <typename TZ, typename SA, typename SB, int RP>
+template <typename TZ, typename SA, typename SB, int RP, bool BF>
 static hipError_t launch_fast_all(hipStream_t s, int ntiles, const Tile* tiles, TZ* Z, int64_t ldz, int nz,
                                   const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld, int64_t w_pstride,
                                   int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P, GroupStrides gs) {
   const int bchunks = kb > 0 ? (kb + 63) / 64 : 1;
   const int nks = ka / 4;
 #define HODLR_LPM(MBV)                                                                                            \
-  return launch_fast_nks<TZ, SA, SB, MBV, RP>(nks, s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,           \
+  return launch_fast_nks<TZ, SA, SB, MBV, RP, BF>(nks, s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,           \
                                                 w_pstride, node_shift, B1, ldb, kb, P, gs)
   switch (kb > 0 ? std::min(kb, 64) / 16 : 0) {
     case 0: HODLR_LPM(0);
@@ -490,7 +520,7 @@ template <typename TZ, typename SA, typename SB>
 hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int tiles_aligned, TZ* Z, int64_t ldz,
                              int nz, const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld,
                              int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
-                             GroupStrides gs) {
+                             GroupStrides gs, int bf) {
   if (ntiles == 0 || nz == 0 || (ka == 0 && kb == 0)) return hipSuccess;
   const int zchunks = (nz + 63) / 64;
   const int bchunks = kb > 0 ? (kb + 63) / 64 : 1;
@@ -508,12 +538,21 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int t
       auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
       const bool pair_ok = ldz % 2 == 0 && (ka == 0 || lda % 2 == 0) && (kb == 0 || ldb % 2 == 0) && al16(Z) &&
                            (ka == 0 || al16(A1)) && (kb == 0 || al16(B1));
-      if ((tiles_aligned & 2) && pair_ok)
-        return launch_fast_all<TZ, SA, SB, 2>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride, node_shift,
-                                              B1, ldb, kb, P, gs);
+      // bfloat16 products only where the factorization uses them (Z and A1 both Y)
+      constexpr bool kBf = std::is_same<SA, TZ>::value;
+      if ((tiles_aligned & 2) && pair_ok) {
+        if (kBf && bf)
+          return launch_fast_all<TZ, SA, SB, 2, true>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride,
+                                                      node_shift, B1, ldb, kb, P, gs);
+        return launch_fast_all<TZ, SA, SB, 2, false>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride,
+                                                     node_shift, B1, ldb, kb, P, gs);
+      }
+      if (kBf && bf)
+        return launch_fast_all<TZ, SA, SB, 1, true>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride,
+                                                    node_shift, B1, ldb, kb, P, gs);
     }
-    return launch_fast_all<TZ, SA, SB, 1>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride, node_shift, B1,
-                                          ldb, kb, P, gs);
+    return launch_fast_all<TZ, SA, SB, 1, false>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride,
+                                                 node_shift, B1, ldb, kb, P, gs);
   }
   const int mbn = kb > 0 ? (min(kb, 64) + 15) / 16 : 1;
   const size_t smem_red = kb > 0 ? sizeof(TZ) * 4 * 16 * mbn * 64 : 0;
@@ -540,7 +579,7 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int t
 #define HODLR_LP_INST(TZ, SA, SB)                                                                             \
   template hipError_t launch_level_pass<TZ, SA, SB>(hipStream_t, int, const Tile*, int, TZ*, int64_t, int, const SA*, \
                                                     int64_t, int, const TZ*, int64_t, int64_t, int,           \
-                                                    const SB*, int64_t, int, TZ*, GroupStrides);
+                                                    const SB*, int64_t, int, TZ*, GroupStrides, int);
 HODLR_LP_INST(double, double, double)
 HODLR_LP_INST(float, float, double)
 HODLR_LP_INST(float, double, float)

@@ -1,4 +1,5 @@
-// MFMA helpers shared by the HIP kernels (f64 16x16x4 and f32 16x16x4).
+// MFMA helpers shared by the HIP kernels (f64 16x16x4, f32 16x16x4 and
+// bf16 16x16x16 with FP32 accumulation).
 //
 // Operand layouts (wave of 64 lanes, li = lane % 16, lq = lane / 16):
 //   A (16 x 4):  lane holds A[li][lq]
@@ -35,6 +36,41 @@ struct Mfma<float> {
   static __device__ __forceinline__ int crow(int lq, int t) { return 4 * lq + t; }
   static __device__ __forceinline__ constexpr int crow_u(int t) { return t; }
   static __device__ __forceinline__ int crow_l(int lq) { return 4 * lq; }
+};
+
+// Four 16x16x4 K-steps into one accumulator, c += sum_s (step s), where step s
+// takes a[s] as the lane's A value and b[s] as its B value (whatever K index
+// each step stands for).  BF = false issues the four steps in order.  BF = true
+// rounds the operands to bfloat16 (nearest, ties to even) and issues one
+// 16x16x16 bf16 MFMA with FP32 accumulation: that instruction takes four K
+// values per lane, and a lane's four A values meet the same lane's four B
+// values (element j of lane (li, lq) is K index 4 lq + j on both sides), so
+// packing step s as element j = s pairs every A value with the B value of its
+// own step and the sum over K is that of the four steps.
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+template <typename T, bool BF>
+struct Mma16 {
+  typedef typename Mfma<T>::V V;
+  static __device__ __forceinline__ V mma(const T (&a)[4], const T (&b)[4], V c) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) c = Mfma<T>::mma(a[ks], b[ks], c);
+    return c;
+  }
+};
+template <>
+struct Mma16<float, true> {
+  typedef f4 V;
+  static __device__ __forceinline__ V mma(const float (&a)[4], const float (&b)[4], V c) {
+    b4 av, bv;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      av[j] = (__bf16)a[j];
+      bv[j] = (__bf16)b[j];
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, av), __builtin_bit_cast(s4, bv), c, 0, 0,
+                                                      0);
+  }
 };
 
 // Raw buffer access: a lane-uniform base in a buffer resource (scalar

@@ -241,6 +241,42 @@ def test_fp32_factor_with_refinement(name, storage):
     assert _rel(lam, O.solve_adjoint(H, B)) < 1e-9
 
 
+CASES_BF16 = ["cfg0_like", "ragged_L6", "deep_L8", "leaf128_L5_r64", "leaf256_L3"]
+
+
+@pytest.mark.parametrize("storage", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name", CASES_BF16)
+def test_bf16_factor_with_refinement(name, storage):
+    """BF16 factorization (bfloat16 operands, FP32 accumulation, FP32 panels and
+    K) refined in FP64 to a 1e-10 residual, forward and adjoint.  The unrefined
+    BF16 solve must be measurably less accurate than the FP32 one (the operands
+    really are rounded) yet within kappa * u_bf16 of the oracle."""
+    _say(f"bf16 factor {name}, storage {storage}")
+    inp, H, A = _build_st(name, 17, storage)
+    B = _rhs(H.N, 3, 18)
+    hd = H_()
+    Xo = O.solve(O.factor(H), B)
+    F32 = hd.factor(A, "fp32")
+    e32 = _rel(_from_dev(F32.solve(_to_dev(B))), Xo)
+    del F32
+    F = hd.factor(A, "bf16")
+    ebf = _rel(_from_dev(F.solve(_to_dev(B))), Xo)
+    _say(f"  plain solve rel error: fp32 {e32:.2e}, bf16 {ebf:.2e}")
+    assert ebf < 5e-2
+    assert ebf > 4 * e32
+    st = {}
+    x = _from_dev(F.solve(_to_dev(B), refine=True, tol=1e-10, stats=st))
+    _say(f"  refined: {st}")
+    assert st["converged"] and st["relres"] <= 1e-10
+    assert O.relres(H, x, B) <= 1e-10
+    assert _rel(x, Xo) < 1e-9
+    sta = {}
+    lam = _from_dev(F.solve_adjoint(_to_dev(B), refine=True, tol=1e-10, stats=sta))
+    _say(f"  adjoint refined: {sta}")
+    assert sta["converged"] and O.relres(O.transpose(H), lam, B) <= 1e-10
+    assert _rel(lam, O.solve_adjoint(H, B)) < 1e-9
+
+
 def test_refinement_reports_non_convergence():
     """kappa * u_fp32 >> 1: refinement must not claim success."""
     _say("refine non-convergence")
@@ -285,7 +321,7 @@ def test_bitwise_determinism():
     inp, H, A = _build("leaf256_L3", seed=10)
     B = _to_dev(_rhs(H.N, 2, 13))
     hd = H_()
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16"):
         F1 = hd.factor(A, prec)
         F2 = hd.factor(A, prec)
         assert torch.equal(F1.y_big(), F2.y_big())
