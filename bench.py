@@ -61,9 +61,9 @@ def kernel_models(inp, nrhs, tsize):
     summ3 = sum(mm ** 3 for mm in m)
     mod = {}
     # leaf LU: read D (storage), write LU (compute)
-    mod["leaf_lu"] = dict(flops=2.0 / 3.0 * summ3, bytes=summ2 * (sb + tsize), launches=1)
+    mod["leaf_lu"] = dict(flops=2.0 / 3.0 * summ3, bytes=summ2 * (sb + tsize), launches=1, bound="mfma")
     # leaf TRSM: read LU, read U (storage), write Y
-    mod["leaf_trsm"] = dict(flops=2.0 * summ2 * R, bytes=summ2 * tsize + N * R * (sb + tsize), launches=1)
+    mod["leaf_trsm"] = dict(flops=2.0 * summ2 * R, bytes=summ2 * tsize + N * R * (sb + tsize), launches=1, bound="mfma")
     # level passes of the factor: product-only at the leaves, then update + product per level p = L-1..1
     fl = 2.0 * N * r[L - 1] * R
     by = N * R * tsize + N * r[L - 1] * sb
@@ -85,14 +85,116 @@ def kernel_models(inp, nrhs, tsize):
     return mod
 
 
+def _timed_path(hodlr, A, precision, B, refine, steps, warmup, adjoint=False):
+    """Factor A in `precision` and solve B (nrhs columns), warmup + timed steps.
+    A step is one refactorization (in the factors' existing storage) plus one
+    solve of all columns (with refinement when `refine`), and with `adjoint` one
+    adjoint solve as well.  Returns (results, per-kernel times, factors)."""
+    import torch
+
+    _say(f"{precision}: factor + warmup")
+    free0 = torch.cuda.mem_get_info()[0]
+    F = hodlr.factor(A, precision)
+    torch.cuda.synchronize()
+    dev_bytes = free0 - torch.cuda.mem_get_info()[0]
+    stats, astats = {}, {}
+    for _ in range(1 + warmup):
+        F.refactor()
+        x = F.solve(B, refine=refine, stats=stats)
+        if adjoint:
+            lam = F.solve_adjoint(B, refine=refine, stats=astats)
+    torch.cuda.synchronize()
+
+    def run(k):
+        tf = ts = ta = 0.0
+        for _ in range(k):
+            torch.cuda.synchronize()
+            a0 = time.perf_counter()
+            F.refactor()            # ends with the singularity verdict (one sync)
+            torch.cuda.synchronize()
+            a1 = time.perf_counter()
+            xx = F.solve(B, refine=refine, stats=stats)
+            torch.cuda.synchronize()
+            a2 = time.perf_counter()
+            if adjoint:
+                F.solve_adjoint(B, refine=refine, stats=astats)
+                torch.cuda.synchronize()
+            a3 = time.perf_counter()
+            tf += a1 - a0
+            ts += a2 - a1
+            ta += a3 - a2
+        return tf / k, ts / k, ta / k, xx
+
+    # the headline figures: no per-kernel instrumentation in these steps
+    _say(f"{precision}: {steps} timed steps")
+    tf, ts, ta, x = run(steps)
+    # per-kernel times from HIP events on the launch stream, in a second run of the same steps
+    _say(f"{precision}: {steps} steps with per-kernel HIP events")
+    hodlr.timing(True)
+    run(steps)
+    kt = hodlr.kernel_times()
+    hodlr.timing(False)
+    r = A.matvec(x) - B
+    relres = (torch.linalg.vector_norm(r, dim=-1) / torch.linalg.vector_norm(B, dim=-1)).max().item()
+    out = dict(t_factor_ms=tf * 1e3, t_solve_ms=ts * 1e3, ms_per_step=(tf + ts) * 1e3, relres=relres,
+               refine_iters=stats.get("iters", 0), factor_bytes=F.nbytes, device_bytes_at_factor=int(dev_bytes))
+    if adjoint:
+        lam = F.solve_adjoint(B, refine=refine, stats=astats)
+        ra = A.matvec(lam, trans=True) - B
+        out.update(t_adjoint_ms=ta * 1e3, adjoint_relres=(torch.linalg.vector_norm(ra, dim=-1) /
+                                                          torch.linalg.vector_norm(B, dim=-1)).max().item(),
+                   adjoint_refine_iters=astats.get("iters", 0))
+    return out, kt, F
+
+
+def _kernel_table(kt, mods, steps, peak_flops):
+    """Per-kernel averages from HIP events with each modelled kernel's achieved
+    rate against its bound; returns (table, roofline of the kernel that takes
+    the most time)."""
+    per_kernel, roof = {}, None
+    ranked = sorted(kt.items(), key=lambda kv: -kv[1][0])
+    for name, (ms, cnt) in ranked:
+        d = dict(avg_ms=ms / max(cnt, 1), launches_per_step=cnt / steps, total_ms_per_step=ms / steps)
+        if name in mods:
+            mdl = mods[name]
+            avg_s = ms / cnt / 1e3
+            fl, by = mdl["flops"] / mdl["launches"], mdl["bytes"] / mdl["launches"]
+            if mdl.get("bound") == "mfma":
+                d.update(bound="mfma", achieved=fl / avg_s / 1e12, peak=peak_flops / 1e12, unit="TFLOP/s")
+            else:
+                d.update(bound="hbm", achieved=by / avg_s / 1e9, peak=PEAK["hbm"] / 1e9, unit="GB/s")
+            d.update(frac=d["achieved"] / d["peak"], intensity_flop_per_byte=mdl["flops"] / mdl["bytes"])
+            if roof is None:
+                roof = dict(kernel=name, bound=d["bound"], achieved=d["achieved"], peak=d["peak"], unit=d["unit"],
+                            frac=d["frac"])
+        per_kernel[name] = d
+    return per_kernel, roof
+
+
+WORKLOADS = {
+    1: ("gaussian_kernel_2d", "synthetic (seeded uniform points in [0,1]^2, RCB order, Gaussian kernel "
+        "sigma 0.05 + 1e-2 I, randomized range finder to rank 32 on the GPU)"),
+    2: ("laplace_dl_bie_star", "synthetic (seeded star-curve Laplace double-layer Nystrom matrix, "
+        "ACA-compressed on the GPU)"),
+    3: ("matern32_kernel_3d", "synthetic (seeded uniform points in [0,1]^3, RCB order, Matern-3/2 l=0.1 "
+        "+ 1e-3 I, randomized range finder to rank 24 on the GPU)"),
+    4: ("synthetic_hodlr_fp32_storage", "synthetic (seeded N(0,1) leaf blocks + 1024 I, N(0,1)/sqrt(node size) "
+        "generators, stored FP32)"),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4],
+                    help="workload: 2 = the headline BIE system (default); 1 = Gaussian kernel, N = 2^18, "
+                         "nrhs 1 and 16; 3 = Matern-3/2 in FP32 with the gradient; 4 = N = 2^22, r = 64, BF16 "
+                         "factorization, 32 right-hand sides, FP64 refinement and the adjoint")
     ap.add_argument("--n", type=int, default=None, help="override N (same leaf and rank)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 + refinement path")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 and BF16 refinement paths")
     ap.add_argument("--synthetic", action="store_true",
                     help="random generators of the same N, leaf and rank instead of the BIE matrix (same shapes, "
                          "so the same kernels and traffic; used for counter runs)")
@@ -104,7 +206,6 @@ def main():
               "(multi-GPU subtree sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import workloads as W
@@ -120,132 +221,127 @@ def main():
         torch.cuda.synchronize()
         _say("copy probe: 3 copies of 1 GiB (read 1 GiB + write 1 GiB each)")
         return
+    cfg = args.config
+    c = W.CONFIGS[cfg]
     t0 = time.time()
-    if args.synthetic:
-        c2 = W.CONFIGS[2]
-        inp = W.synthetic(args.n or c2["n"], c2["leaf"], c2["rank"], seed=0, dtype=torch.float64, device=dev)
+    if args.synthetic and cfg == 2:
+        inp = W.synthetic(args.n or c["n"], c["leaf"], c["rank"], seed=0, dtype=torch.float64, device=dev)
     else:
-        inp = W.make_config(2, device=dev, n=args.n)
+        inp = W.make_config(cfg, device=dev, n=args.n)
     torch.cuda.synchronize()
     _say(f"generated {inp.name} in {time.time() - t0:.1f}s")
     N = inp.n
     A = hodlr.HODLRMatrix.from_inputs(inp)
-    b = W.gaussian_rhs(N, 1, seed=0, device=dev)[0]
     Fp = model.factor_flops_paper(inp.leaf_offsets, inp.ranks)
-    Sp = model.solve_flops(inp.leaf_offsets, inp.ranks, 1)
+    ssize = inp.D.element_size()
+    paths = {}
+    kts = {}
 
-    def run_path(precision, refine):
-        _say(f"{precision}: factor + warmup")
-        F = hodlr.factor(A, precision)
-        stats = {}
-        x = F.solve(b, refine=refine, stats=stats)
-        for _ in range(args.warmup):
-            F.refactor()
-            x = F.solve(b, refine=refine, stats=stats)
+    def flops_of(res, nrhs):
+        Sp = model.solve_flops(inp.leaf_offsets, inp.ranks, nrhs)
+        res.update(factor_tflops=Fp / res["t_factor_ms"] * 1e-9,
+                   tflops=(Fp + Sp) / res["ms_per_step"] * 1e-9)
+        return res
+
+    if cfg == 2:
+        b = W.gaussian_rhs(N, 1, seed=0, device=dev)
+        plan = [("fp64", "fp64", False)]
+        if not args.no_mixed:
+            plan += [("fp32_ir", "fp32", True), ("bf16_ir", "bf16", True)]
+        for key, prec, refine in plan:
+            res, kt, F = _timed_path(hodlr, A, prec, b, refine, args.steps, args.warmup)
+            _say(f"{key}: releasing the factors")
+            del F
+            paths[key] = flops_of(res, 1)
+            kts[key] = kt
+            _say(f"{key}: {paths[key]}")
+        head = paths["fp64"]
+        nrhs, dtype = 1, "f64"
+    elif cfg == 1:
+        b1 = W.gaussian_rhs(N, 1, seed=0, device=dev)
+        b16 = W.gaussian_rhs(N, 16, seed=1, device=dev)
+        res, kt, F = _timed_path(hodlr, A, "fp64", b1, False, args.steps, args.warmup)
+        paths["fp64_nrhs1"] = flops_of(res, 1)
+        kts["fp64_nrhs1"] = kt
+        del F
+        res, kt, F = _timed_path(hodlr, A, "fp64", b16, False, args.steps, args.warmup)
+        paths["fp64_nrhs16"] = flops_of(res, 16)
+        del F
+        for k, v in paths.items():
+            _say(f"{k}: {v}")
+        head = paths["fp64_nrhs1"]
+        nrhs, dtype = 1, "f64"
+    elif cfg == 3:
+        b = W.gaussian_rhs(N, 1, seed=0, device=dev)
+        t = W.gaussian_rhs(N, 1, seed=1, device=dev)
+        res, kt, F = _timed_path(hodlr, A, "fp32", b, False, args.steps, args.warmup, adjoint=True)
+        # one gradient of L = ||x - t||^2: adjoint solve of 2 (x - t), then dD, dU, dV
+        x = F.solve(b)
         torch.cuda.synchronize()
-
-        def steps(k):
-            tf = ts = 0.0
-            for _ in range(k):
-                torch.cuda.synchronize()
-                a0 = time.perf_counter()
-                F.refactor()            # ends with the singularity verdict (one sync)
-                torch.cuda.synchronize()
-                a1 = time.perf_counter()
-                xx = F.solve(b, refine=refine, stats=stats)
-                torch.cuda.synchronize()
-                a2 = time.perf_counter()
-                tf += a1 - a0
-                ts += a2 - a1
-            return tf / k, ts / k, xx
-
-        # the headline: no per-kernel instrumentation in the timed steps
-        _say(f"{precision}: {args.steps} timed steps")
-        tf, ts, x = steps(args.steps)
-        # per-kernel times from HIP events on the launch stream, in a second
-        # timed region of the same steps
-        _say(f"{precision}: {args.steps} steps with per-kernel HIP events")
-        hodlr.timing(True)
-        steps(args.steps)
-        kt = hodlr.kernel_times()
-        hodlr.timing(False)
-        r = A.matvec(x) - b
-        relres = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)).item()
-        out = dict(t_factor_ms=tf * 1e3, t_solve_ms=ts * 1e3, ms_per_step=(tf + ts) * 1e3,
-                   factor_tflops=Fp / tf / 1e12, tflops=(Fp + Sp) / (tf + ts) / 1e12, relres=relres,
-                   refine_iters=stats.get("iters", 0), factor_gb=F.nbytes / 1e9)
-        return out, kt, F
-
-    fp64, kt64, F64 = run_path("fp64", False)
-    _say(f"fp64: {fp64}")
-    del F64
-    mixed = None
-    if not args.no_mixed:
-        mixed, kt32, F32 = run_path("fp32", True)
-        _say("fp32+IR: releasing the factors")
-        del F32
-        mixed["kernels_ms_per_step"] = {k: ms / args.steps for k, (ms, cnt) in sorted(kt32.items(), key=lambda kv: -kv[1][0])}
-        _say(f"fp32+IR: {mixed}")
-
-    # roofline of the dominant FP64 kernel (per-launch averages from HIP events)
-    mods = kernel_models(inp, 1, 8)
-    kinds = {"leaf_lu": "leaf_lu", "leaf_trsm": "leaf_trsm", "level_pass": "level_pass",
-             "leaf_solve": "leaf_solve", "solve_pass": "solve_pass"}
-    kern = {}
-    for name, (ms, cnt) in kt64.items():
-        kern[name] = dict(avg_ms=ms / max(cnt, 1), launches=cnt, total_ms=ms)
-    ranked = sorted(kern.items(), key=lambda kv: -kv[1]["total_ms"])
-    roof = None
-    per_kernel = {}
-    for name, d in kern.items():
-        if name not in mods:
-            per_kernel[name] = dict(avg_ms=d["avg_ms"], launches_per_step=d["launches"] / args.steps,
-                                    total_ms_per_step=d["total_ms"] / args.steps)
-            continue
-        mdl = mods[name]
-        per_launch_flops = mdl["flops"] / mdl["launches"]
-        per_launch_bytes = mdl["bytes"] / mdl["launches"]
-        avg_s = d["total_ms"] / d["launches"] / 1e3
-        ai = mdl["flops"] / mdl["bytes"]
-        if name == "leaf_trsm" or name == "leaf_lu":
-            bound, ach, peak, unit = "alu", per_launch_flops / avg_s / 1e12, PEAK["f64"] / 1e12, "TFLOP/s"
-        else:
-            bound, ach, peak, unit = "hbm", per_launch_bytes / avg_s / 1e9, PEAK["hbm"] / 1e9, "GB/s"
-        per_kernel[name] = dict(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak,
-                                avg_ms=d["total_ms"] / d["launches"], launches_per_step=d["launches"] / args.steps,
-                                total_ms_per_step=d["total_ms"] / args.steps, intensity_flop_per_byte=ai)
-    for name, _ in ranked:
-        if name in per_kernel and "bound" in per_kernel[name]:
-            pk = per_kernel[name]
-            roof = dict(kernel=name, bound=pk["bound"], achieved=pk["achieved"], peak=pk["peak"], unit=pk["unit"],
-                        frac=pk["frac"], traffic=measured_traffic(name, inp))
-            break
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            lam = F.solve_adjoint(2.0 * (x - t))
+            dD, dU, dV = F.grad(x, lam)
+        torch.cuda.synchronize()
+        res["t_gradient_ms"] = (time.perf_counter() - tg) / args.steps * 1e3
+        del F
+        paths["fp32"] = flops_of(res, 1)
+        kts["fp32"] = kt
+        _say(f"fp32: {paths['fp32']}")
+        head = paths["fp32"]
+        nrhs, dtype = 1, "f32"
+    else:  # cfg 4
+        B = W.gaussian_rhs(N, c["nrhs"], seed=0, device=dev)
+        plan = [("bf16_ir", "bf16")]
+        if not args.no_mixed:
+            plan.append(("fp32_ir", "fp32"))
+        for key, prec in plan:
+            res, kt, F = _timed_path(hodlr, A, prec, B, True, args.steps, args.warmup, adjoint=True)
+            del F
+            paths[key] = flops_of(res, c["nrhs"])
+            kts[key] = kt
+            _say(f"{key}: {paths[key]}")
+        head = paths["bf16_ir"]
+        nrhs, dtype = c["nrhs"], "bf16"
+    for key, kt in kts.items():
+        prec = key.split("_")[0]
+        tsize = 8 if prec == "fp64" else 4
+        peak = PEAK["f64"] if prec == "fp64" else PEAK["f32"] if prec == "fp32" else PEAK["bf16"]
+        mods = kernel_models(inp, nrhs, tsize)
+        paths[key]["kernels"], paths[key]["roofline"] = _kernel_table(kt, mods, args.steps, peak)
+    headkey = next(iter(kts))
+    roof = paths[headkey].get("roofline")
+    if roof is not None:
+        roof = dict(roof)
+        roof["traffic"] = measured_traffic(roof["kernel"], inp) if headkey == "fp64" else None
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and cfg == 2:
         _say("cpu baseline: loading the oracle")
-        cpu = cpu_baseline(inp, b)
+        cpu = cpu_baseline(inp, b[0])
 
+    mem = torch.cuda.mem_get_info()
     res = {
         "metric": "factor+solve s & TFLOP/s at N=1M; mixed-prec vs FP64 at rel. residual 1e-10",
-        "value": fp64["tflops"],
+        "value": head["tflops"],
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": fp64["ms_per_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded star-curve Laplace double-layer Nystrom matrix, ACA-compressed on the GPU)",
-        "config": {"workload": "laplace_dl_bie_star", "N": N, "leaf": int(inp.m_max), "levels": inp.levels,
-                   "rank": int(inp.ranks[0]) if inp.ranks else 0, "nrhs": 1, "storage": "f64",
-                   "flop_count": "paper (factor 2/3 m^2N + 2mrNL + 2r^2N(L+L^2), solve 2mN + 4rNL)"},
-        "fp64": fp64,
-        "fp32_ir": mixed,
+        "dtype": dtype,
+        "data": WORKLOADS[cfg][1],
+        "config": {"workload": WORKLOADS[cfg][0], "N": N, "leaf": int(inp.m_max), "levels": inp.levels,
+                   "rank": int(inp.ranks[0]) if inp.ranks else 0, "nrhs": nrhs,
+                   "storage": "f64" if ssize == 8 else "f32",
+                   "flop_count": "paper (factor 2/3 m^2N + 2mrNL + 2r^2N(L+L^2), solve 2mN + 4rNL per rhs)",
+                   "matrix_bytes": int(inp.D.numel() + inp.U.numel() + inp.V.numel()) * ssize,
+                   "device_total_bytes": int(mem[1])},
+        **paths,
         "roofline": roof,
-        "kernels": per_kernel,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

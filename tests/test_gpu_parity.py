@@ -242,6 +242,11 @@ def test_fp32_factor_with_refinement(name, storage):
 
 
 CASES_BF16 = ["cfg0_like", "ragged_L6", "deep_L8", "leaf128_L5_r64", "leaf256_L3"]
+# deep_L8 (16-row leaves, every rank below 16) has no contraction that fills a
+# 16 x 16 x 16 bfloat16 block: its leaf LU has no trailing block updates, its
+# leaf solves one row block per wave and its level passes take the general
+# (FP32) kernel, so its BF16 factorization is the FP32 one exactly
+BF16_FP32_ONLY = {"deep_L8"}
 
 
 @pytest.mark.parametrize("storage", [torch.float64, torch.float32])
@@ -263,7 +268,10 @@ def test_bf16_factor_with_refinement(name, storage):
     ebf = _rel(_from_dev(F.solve(_to_dev(B))), Xo)
     _say(f"  plain solve rel error: fp32 {e32:.2e}, bf16 {ebf:.2e}")
     assert ebf < 5e-2
-    assert ebf > 4 * e32
+    if name in BF16_FP32_ONLY:
+        assert ebf == e32
+    else:
+        assert ebf > 4 * e32
     st = {}
     x = _from_dev(F.solve(_to_dev(B), refine=True, tol=1e-10, stats=st))
     _say(f"  refined: {st}")
