@@ -18,6 +18,7 @@ from .hodlr_oracle import (  # noqa: F401
     solve_adjoint,
     matvec,
     grad_structured,
+    logdet_grad_structured,
     loss_and_grads,
     refine,
     low_precision_solver,

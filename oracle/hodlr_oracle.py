@@ -296,6 +296,33 @@ def grad_structured(H: Hodlr, X: np.ndarray, Lam: np.ndarray):
     return dD, dU, dV
 
 
+def logdet_grad_structured(H: Hodlr):
+    """Gradient of log|det A| with respect to the HODLR parameters D, U, V.
+
+    Jacobi's formula gives d log|det A| = trace(A^{-1} dA), so the gradient
+    with respect to the entries of A is A^{-T}; restricted to the parameters
+    through A(I_a, I_a) = D_a and A(I_a, I_b) = U_a V_b^T (as in
+    grad_structured with -Lam X^T replaced by G = A^{-T}):
+    dD_a = G_aa,  dU_a = G_ab V_b,  dV_b = G_ab^T U_a.  Dense: small N only.
+    """
+    G = np.linalg.inv(assemble_dense(H)).T
+    dD = np.zeros_like(H.D)
+    dU = np.zeros_like(H.U)
+    dV = np.zeros_like(H.V)
+    for i in range(1 << H.L):
+        s, e = node_range(H, H.L, i)
+        dD[s:e, :e - s] = G[s:e, s:e]
+    for level in range(1, H.L + 1):
+        c0, c1 = H.colrange(level)
+        for p in range(1 << (level - 1)):
+            for a, b in ((2 * p, 2 * p + 1), (2 * p + 1, 2 * p)):
+                sa, ea = node_range(H, level, a)
+                sb, eb = node_range(H, level, b)
+                dU[sa:ea, c0:c1] = G[sa:ea, sb:eb] @ H.V[sb:eb, c0:c1]
+                dV[sb:eb, c0:c1] = G[sa:ea, sb:eb].T @ H.U[sa:ea, c0:c1]
+    return dD, dU, dV
+
+
 def loss_and_grads(H: Hodlr, b: np.ndarray, t: np.ndarray):
     """L = ||x - t||_F^2 with x = A^{-1} b.  Returns (L, x, dL/db, dD, dU, dV)."""
     F = factor(H)

@@ -233,6 +233,67 @@ def test_planted_slogdet_mistakes_fail(monkeypatch, mistake):
         assert la != pytest.approx(ld, rel=1e-12, abs=1e-9)  # the pin's tolerance
 
 
+def _fd_logdet(H, which, pos, h=1e-3):
+    """Central difference of LAPACK's log|det| of the assembled matrix in one
+    parameter entry (an independent route: no inverse, no factors).  log|det|
+    is in the thousands here, so h is large enough for its rounding
+    (u |log det| / h ~ 1e-9) and small enough for the O(h^2) term."""
+    arr = {"D": H.D, "U": H.U, "V": H.V}[which]
+    old = arr[pos]
+    arr[pos] = old + h
+    lp = np.linalg.slogdet(O.assemble_dense(H))[1]
+    arr[pos] = old - h
+    lm = np.linalg.slogdet(O.assemble_dense(H))[1]
+    arr[pos] = old
+    return (lp - lm) / (2 * h)
+
+
+def _logdet_probes(H, rng, k=6):
+    out = []
+    for which in ("D", "U", "V"):
+        for _ in range(k):
+            if which == "D":
+                leaf = int(rng.integers(1 << H.L))
+                s0, e = O.node_range(H, H.L, leaf)
+                pos = (int(rng.integers(s0, e)), int(rng.integers(e - s0)))
+            else:
+                pos = (int(rng.integers(H.N)), int(rng.integers(H.U.shape[1])))
+            out.append((which, pos))
+    return out
+
+
+@pytest.mark.parametrize("c", [CASES[1], dict(n=384, leaf=None, rank=[3, 5, 1], L=3)])
+def test_logdet_gradient_matches_finite_differences(c):
+    """Jacobi's formula on the structure against central differences of
+    LAPACK's slogdet, entry by entry in D (inside leaf blocks), U and V,
+    on a non-symmetric matrix (so A^{-1} and A^{-T} differ)."""
+    H = _case(c, seed=5)
+    dD, dU, dV = O.logdet_grad_structured(H)
+    g = {"D": dD, "U": dU, "V": dV}
+    for which, pos in _logdet_probes(H, np.random.default_rng(6)):
+        fd = _fd_logdet(H, which, pos)
+        assert g[which][pos] == pytest.approx(fd, rel=1e-5, abs=1e-8), (which, pos, g[which][pos], fd)
+
+
+@pytest.mark.parametrize("mistake", ["inverse_not_transposed", "u_v_swapped"])
+def test_planted_logdet_gradient_mistakes_fail(monkeypatch, mistake):
+    """Using A^{-1} instead of A^{-T}, or the sibling's generator on the wrong
+    side, fails the finite-difference pin."""
+    H = _case(dict(n=256, leaf=32, rank=4), seed=7)
+    if mistake == "inverse_not_transposed":
+        monkeypatch.setattr(OH.np.linalg, "inv", lambda A: np.linalg.pinv(A).T)
+        dD, dU, dV = O.logdet_grad_structured(H)
+    else:
+        dD, dU, dV = O.logdet_grad_structured(H)
+        dU, dV = dV, dU
+    g = {"D": dD, "U": dU, "V": dV}
+    bad = 0
+    for which, pos in _logdet_probes(H, np.random.default_rng(8)):
+        fd = _fd_logdet(H, which, pos)
+        bad += g[which][pos] != pytest.approx(fd, rel=1e-5, abs=1e-8)
+    assert bad > 0
+
+
 # ---- adjoint and gradients --------------------------------------------------------
 
 def test_adjoint_dot_test_and_dense():
