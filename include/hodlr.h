@@ -204,6 +204,40 @@ hodlr_status hodlr_grad(const hodlr_factors *F, int64_t nrhs, const double *X, i
  * eq. "e:recursion") into Y as FP64 (ldy >= N). */
 hodlr_status hodlr_factors_y(const hodlr_factors *F, double *Y, int64_t ldy, void *stream);
 
+/* Sign and natural logarithm of |det A| from the stored factors (Section
+ * III-E, "Determinant"): A = D F_L ... F_1, so det A is the product of the
+ * leaf determinants and of det F_g over the parents g, and by Sylvester's
+ * determinant theorem det F_g = (-1)^r det K_g (K_g of eq. "e:k" is the
+ * 2x2 block factor's small matrix with its two row blocks exchanged).  Each
+ * determinant is the product of its LU pivots with the sign of its
+ * interchanges.  Host outputs: *sign in {-1, 0, +1} (0 when a pivot is
+ * exactly zero, *logabs then -inf), *logabs summed in FP64 in a fixed order
+ * (deterministic).  For F32/BF16 factors the pivots are FP32.  Synchronises
+ * `stream` once. */
+hodlr_status hodlr_logdet(const hodlr_factors *F, double *sign, double *logabs, void *stream);
+
+/* Gradient of log|det A| with respect to the HODLR parameters (Section III-E
+ * "Determinant" differentiated): by Jacobi's formula the gradient with
+ * respect to A is A^{-T}, restricted here to the parameters through
+ * A(I_a, I_a) = D_a and A(I_a, I_b) = U_a V_b^T:
+ *   dD_a = (A^{-T})_aa,  dU_a = (A^{-T})_ab V_b,  dV_b = ((A^{-T})_ab)^T U_a.
+ * Computed through the factorization, never forming A^{-1}: with
+ * T_a = V_a^T Y_a and P_a the a-block of K_g^{-1} (g the parent of a),
+ * log|det A| = sum log|det D| + sum log|det K|, so
+ *   dD_a = D_a^{-T} - Lam(I_a, :) Y(I_a, :)^T,
+ *   dU_m = Lam(I_m, c_l) - Lam(I_m, 1:R_{l-1}) Y(I_n, 1:R_{l-1})^T V_n,
+ *   dV_n = Y(I_n, c_l) P_n - Y(I_n, 1:R_{l-1}) Lam(I_m, 1:R_{l-1})^T U_m
+ * for siblings (m, n) of level l, where Lam(I_a, c_l) = A_a^{-T} V_a P_a^T
+ * comes from Y_big of A^T (a second factorization, of D^T with U and V
+ * exchanged).  dD, dU, dV are written in the storage type and layout of F's
+ * D, U, V (as hodlr_grad).  Arithmetic: the factors' precision for the
+ * solves, FP64 for the assembly.  Needs the original D, U, V
+ * (HODLR_ERR_ARG on in-place factors), HODLR_ERR_SINGULAR on a singular
+ * factorization.  Allocates temporaries (two FP64 projection trees of
+ * (2^{L+1} - 2) R^2 entries, four N x R FP64 blocks, the factors of A^T) and
+ * synchronises `stream` before freeing them. */
+hodlr_status hodlr_logdet_grad(const hodlr_factors *F, void *dD, void *dU, void *dV, void *stream);
+
 /* Device bytes owned by F: the factors, the factorization's workspace and
  * the solve workspaces of every stream F was used on. */
 size_t hodlr_factor_bytes(const hodlr_factors *F);

@@ -290,8 +290,11 @@ __device__ __forceinline__ void form_k(T* K, const T* Pa, const T* Pb, int r, in
 // block).  Step j eliminates column j from every other row, including the
 // rows pivoted earlier, and scales the pivot row; afterwards the augmented
 // row of the row pivoted at step j is row j of K^{-1}, written to K (col-major).
+// spiv[j] records the position the row pivoted at step j came from (an
+// interchange with position j, as LAPACK's ipiv) and spv[j] its pivot value:
+// the pivots are those of LU with partial pivoting, so they give det K.
 template <typename T>
-__device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, unsigned long long* info,
+__device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, int* spiv, T* spv, unsigned long long* info,
                                          unsigned long long info_base) {
   __shared__ T s_l[2][64];
   __shared__ int s_pl[2][2];  // pivot lane, pivot value nonzero
@@ -327,6 +330,8 @@ __device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, unsigned
         if (lane == 0) {
           s_pl[sb][0] = plane;
           s_pl[sb][1] = nz;
+          spiv[j] = bk;
+          spv[j] = pv;
           if (!nz) atomicMin(info, info_base | (unsigned long long)j);
         }
       }
@@ -540,7 +545,8 @@ __global__ __launch_bounds__(kCfThreads) void couple_dinv_kernel(int n2, int kp,
 template <typename T>
 __global__ __launch_bounds__(kCfThreads) void couple_factor_inv_kernel(int r, int Rp, const T* __restrict__ segs,
                                                                        const int32_t* __restrict__ seg_start,
-                                                                       T* __restrict__ Kinv, T* __restrict__ W,
+                                                                       T* __restrict__ Kinv, int32_t* __restrict__ Kpiv,
+                                                                       T* __restrict__ Kud, T* __restrict__ W,
                                                                        unsigned long long* info, int level, int L) {
   using M = Mfma<T>;
   using V = typename M::V;
@@ -555,12 +561,19 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_inv_kernel(int r, in
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   const T* Pa = segs + (int64_t)seg_start[a] * elems;
   const T* Pb = segs + (int64_t)seg_start[b] * elems;
+  __shared__ int s_piv[64];
+  __shared__ T s_pv[64];
   form_k(K, Pa, Pb, r, Rp, tid);
   __syncthreads();
-  block_gj(K, n2, lane, wid, info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16));
+  block_gj(K, n2, lane, wid, s_piv, s_pv, info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16));
   __syncthreads();
   T* Kg = Kinv + (int64_t)g * n2 * n2;
   for (int e = tid; e < n2 * n2; e += kCfThreads) Kg[e] = K[e];
+  // interchanges and reciprocal pivots, as the LU route stores them (for det K)
+  if (tid < n2) {
+    Kpiv[(int64_t)g * n2 + tid] = s_piv[tid];
+    Kud[(int64_t)g * n2 + tid] = T(1) / s_pv[tid];
+  }
   // B operand: K^{-1}(16 wid + li, 4 ks + lq)
   const bool act = 16 * wid < n2;  // uniform
   T bk[16];
@@ -613,8 +626,8 @@ hipError_t launch_couple_factor(hipStream_t s, int nparents, int r, int kp, int 
     auto ki = couple_factor_inv_kernel<T>;
     hipError_t e = hipFuncSetAttribute((const void*)ki, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_inv);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(ki, dim3(nparents), dim3(kCfThreads), smem_inv, s, r, Rp, segs, d_seg_start, Klu, W, info,
-                       level, L);
+    hipLaunchKernelGGL(ki, dim3(nparents), dim3(kCfThreads), smem_inv, s, r, Rp, segs, d_seg_start, Klu, Kpiv, Kud, W,
+                       info, level, L);
     return hipGetLastError();
   }
   const size_t smem = sizeof(T) * (size_t)4 * r * r;

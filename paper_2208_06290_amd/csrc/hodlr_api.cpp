@@ -157,6 +157,7 @@ struct Workspace {
   double* tree = nullptr;  // matvec projection tree
   double* tree2 = nullptr;
   double* nrm = nullptr;       // norms: part | b2 | r2 | rinf
+  double* ld = nullptr;        // log-determinant: per-item logs | per-item parities | result
   hipEvent_t done = nullptr;   // recorded after the last call's work on `stream`
 };
 
@@ -213,6 +214,7 @@ struct hodlr_factors {
   std::mutex mu;  // guards wsmap; held by refactor for its whole enqueue
   std::map<hipStream_t, std::unique_ptr<Workspace>> wsmap;
   hipEvent_t ready = nullptr;  // recorded after the factorization's last kernel
+  bool singular = false;       // the last factorization met an exactly zero pivot
 };
 
 namespace {
@@ -548,6 +550,7 @@ hodlr_status verdict(hodlr_factors* F, hipStream_t st, hodlr_info* info) {
     info->column = -1;
     info->node = -1;
   }
+  F->singular = h[0] != ~0ull || h[1] != ~0ull;
   if (h[0] != ~0ull) {
     if (info) {
       info->level = F->L;
@@ -590,7 +593,7 @@ Workspace* get_ws(hodlr_factors* F, hipStream_t st) {
 
 // Sizes of the solve-side buffers for nrhs columns (elements).
 struct WsSizes {
-  size_t pmax = 0, segmax = 0, wmax = 0, n = 0, treeN = 0, nrm = 0;
+  size_t pmax = 0, segmax = 0, wmax = 0, n = 0, treeN = 0, nrm = 0, ld = 0;
 };
 WsSizes ws_sizes(const hodlr_factors* F, int nrhs) {
   WsSizes z;
@@ -607,6 +610,10 @@ WsSizes ws_sizes(const hodlr_factors* F, int nrhs) {
   z.n = (size_t)F->n * nrhs;
   z.treeN = std::max<size_t>((((size_t)1 << (L + 1)) - 2) * (size_t)std::max(F->R, 1) * nrhs, 1);
   z.nrm = (size_t)nrhs * (2 * 256 + 8);
+  size_t items = F->nleaf;
+  for (int p = 0; p < L; ++p)
+    if (F->ranks[p] > 0) items += (size_t)1 << p;
+  z.ld = 2 * items + 8;  // doubles: logs, then parities (ints) in the second half, then the result
   return z;
 }
 
@@ -634,6 +641,7 @@ hodlr_status ensure_ws(hodlr_factors* F, Workspace& W, int nrhs) {
   if ((s = M.alloc(&W.tree, z.treeN))) return s;
   if ((s = M.alloc(&W.tree2, z.treeN))) return s;
   if ((s = M.alloc(&W.nrm, z.nrm))) return s;
+  if ((s = M.alloc(&W.ld, z.ld))) return s;
   W.nrhs = nrhs;
   return HODLR_OK;
 }
@@ -1078,6 +1086,186 @@ hodlr_status hodlr_factors_y(const hodlr_factors* F, double* Yo, int64_t ldy, vo
     HL("convert", (launch_convert<double, float>(st, F->n, F->R, static_cast<const float*>(F->Y), F->ldy, Yo, ldy,
                                                  F->gsy)));
   return HODLR_OK;
+}
+
+hodlr_status hodlr_logdet(const hodlr_factors* Fc, double* sign, double* logabs, void* stream) {
+  hodlr_factors* F = const_cast<hodlr_factors*>(Fc);
+  if (!F || !sign || !logabs) return HODLR_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  LogdetLevels lv;
+  for (int p = 0; p < F->L; ++p) {
+    const int r = F->ranks[p];
+    if (r == 0) continue;
+    lv.count[lv.n] = 1 << p;
+    lv.r[lv.n] = r;
+    lv.kp[lv.n] = kpad(r);
+    lv.kvoff[lv.n] = F->kvoff[p];
+    ++lv.n;
+  }
+  if (F->singular) {  // an exactly zero pivot: det A = 0 (later factors are not meaningful)
+    *sign = 0.0;
+    *logabs = -INFINITY;
+    return HODLR_OK;
+  }
+  double res[2] = {0.0, 0.0};
+  hodlr_status s = on_stream(F, st, 1, [&](Workspace& W) -> hodlr_status {
+    size_t items = F->nleaf;
+    for (int p = 0; p < lv.n; ++p) items += lv.count[p];
+    double* logs = W.ld;
+    int* par = reinterpret_cast<int*>(W.ld + items);
+    double* out = W.ld + 2 * items;
+    if (F->compute == HODLR_F64)
+      HL("logdet", (launch_logdet<double>(st, F->nleaf, F->ldl, F->d_off, tp<double>(F->udinv), F->piv,
+                                          tp<double>(F->Kud), F->Kpiv, lv, logs, par, out)));
+    else
+      HL("logdet", (launch_logdet<float>(st, F->nleaf, F->ldl, F->d_off, tp<float>(F->udinv), F->piv,
+                                         tp<float>(F->Kud), F->Kpiv, lv, logs, par, out)));
+    if (hipMemcpyAsync(res, out, sizeof(res), hipMemcpyDeviceToHost, st) != hipSuccess) return HODLR_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return HODLR_ERR_HIP;
+    return HODLR_OK;
+  });
+  if (s) return s;
+  *logabs = res[0];
+  *sign = std::isinf(res[0]) && res[0] < 0 ? 0.0 : res[1];
+  return HODLR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// K^{-1} diagonal blocks P_a of every level, FP64, Pd at pdoff[l] + a r_l^2
+template <typename T>
+hodlr_status logdet_pblocks(hodlr_factors* F, hipStream_t st, DevMem& M, double* Pd,
+                            const std::vector<int64_t>& pdoff) {
+  for (int p = 0; p < F->L; ++p) {
+    const int r = F->ranks[p];
+    if (r == 0) continue;
+    const int np = 1 << p, n2 = 2 * r, kp = kpad(r);
+    double* Pl = Pd + pdoff[p + 1];
+    if (couple_uses_inverse(r)) {  // K^{-1} is stored (n2 x n2 per parent)
+      HL("logdet_grad", launch_pblocks<T>(st, np, r, tp<T>(F->Klu) + F->koff[p], n2, (int64_t)n2 * n2, Pl));
+    } else {  // K^{-1} = K^{-1} I by the block solver on the stored LU
+      T* X = nullptr;
+      hodlr_status s = M.alloc(&X, (size_t)np * n2 * n2);
+      if (s) return s;
+      HL("logdet_grad", launch_identity_blocks<T>(st, np, n2, X));
+      HL("logdet_grad", launch_block_trsm<T>(st, 0, np, kp, n2, n2, tp<T>(F->Klu) + F->koff[p], F->Kperm + F->kvoff[p],
+                                              tp<T>(F->Kinv) + F->kioff[p], X, (int64_t)np * n2, n2));
+      HL("logdet_grad", launch_pblocks<T>(st, np, r, X, (int64_t)np * n2, n2, Pl));
+    }
+  }
+  return HODLR_OK;
+}
+
+template <typename T, typename S>
+hodlr_status logdet_grad_impl(hodlr_factors* F, hipStream_t st, DevMem& M, void* dDv, void* dUv, void* dVv) {
+  const int L = F->L, R = F->R;
+  const int64_t N = F->n;
+  hodlr_status s;
+  S* dD = static_cast<S*>(dDv);
+  S* dU = static_cast<S*>(dUv);
+  S* dV = static_cast<S*>(dVv);
+  // D^{-T} on the leaf blocks: the adjoint leaf solve of the identity
+  T* E = nullptr;
+  double* E64 = nullptr;
+  if ((s = M.alloc(&E, (size_t)N * F->m_max)) || (s = M.alloc(&E64, (size_t)N * F->m_max))) return s;
+  HL("logdet_grad", launch_identity_leaves<T>(st, F->nleaf, F->m_max, F->d_off, E, N));
+  HL("logdet_grad", (launch_leaf_trsm<T, T>(st, 1, F->nleaf, F->ldl, F->d_off, tp<T>(F->lu), F->lul, F->inplace,
+                                             F->perm, tp<T>(F->invl), E, N, E, N, F->m_max)));
+  HL("logdet_grad", (launch_convert<double, T>(st, N, F->m_max, E, N, E64, N)));
+  if (L == 0 || R == 0) {
+    HL("logdet_grad", launch_grad_leaf<S>(st, F->nleaf, F->m_max, F->d_off, 0, E64, N, E64, N, dD, F->ldd, E64, N));
+    return HODLR_OK;
+  }
+  // Y_big of A^T (D^T, generators exchanged): its level-l block at I_a is A_a^{-T} V_a
+  S* Dt = nullptr;
+  if ((s = M.alloc(&Dt, (size_t)N * F->m_max))) return s;
+  HL("logdet_grad", launch_transpose_leaves<S>(st, F->nleaf, F->m_max, F->d_off, static_cast<const S*>(F->D), F->ldd,
+                                                Dt, N));
+  std::vector<int32_t> rk(F->ranks.begin(), F->ranks.end());
+  hodlr_matrix At{};
+  At.n = N;
+  At.levels = L;
+  At.leaf_offsets = F->off.data();
+  At.ranks = rk.data();
+  At.dtype = F->storage;
+  At.D = Dt;
+  At.ldd = N;
+  At.U = F->V;
+  At.ldu = F->ldv;
+  At.V = F->U;
+  At.ldv = F->ldu;
+  hodlr_factors* FT = nullptr;
+  s = hodlr_factor(&At, F->compute, 0, st, &FT, nullptr);
+  if (s) {
+    if (FT) hodlr_destroy(FT);
+    return s < 0 ? s : HODLR_ERR_SINGULAR;
+  }
+  struct Guard {
+    hodlr_factors* f;
+    ~Guard() { hodlr_destroy(f); }
+  } guard{FT};
+  double *Y64 = nullptr, *Yt64 = nullptr, *Lam = nullptr, *YP = nullptr, *Pd = nullptr, *tV = nullptr, *tU = nullptr;
+  int64_t* d_pdoff = nullptr;
+  std::vector<int64_t> pdoff(L + 2, 0);
+  for (int l = 1; l <= L; ++l) pdoff[l + 1] = pdoff[l] + ((int64_t)1 << l) * F->ranks[l - 1] * F->ranks[l - 1];
+  const size_t nr = (size_t)N * R;
+  const size_t treeN = (((size_t)1 << (L + 1)) - 2) * (size_t)R * R;
+  if ((s = M.alloc(&Y64, nr)) || (s = M.alloc(&Yt64, nr)) || (s = M.alloc(&Lam, nr)) || (s = M.alloc(&YP, nr)) ||
+      (s = M.alloc(&Pd, std::max<size_t>(pdoff[L + 1], 1))) || (s = M.alloc(&d_pdoff, pdoff.size())) ||
+      (s = M.alloc(&tV, treeN)) || (s = M.alloc(&tU, treeN)))
+    return s;
+  if (hipMemcpyAsync(d_pdoff, pdoff.data(), pdoff.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+    return HODLR_ERR_HIP;
+  HL("logdet_grad", (launch_convert<double, T>(st, N, R, tp<T>(F->Y), F->ldy, Y64, N, F->gsy)));
+  HL("logdet_grad", (launch_convert<double, T>(st, N, R, tp<T>(FT->Y), FT->ldy, Yt64, N, FT->gsy)));
+  if ((s = logdet_pblocks<T>(F, st, M, Pd, pdoff))) return s;
+  // Lam(I_a, c_l) = (A_a^{-T} V_a) P_a^T; YP(I_a, c_l) = Y_a P_a
+  HL("logdet_grad", launch_node_mix(st, N, L, R, F->d_off, F->d_rpre, d_pdoff, Pd, 1, Yt64, Lam));
+  HL("logdet_grad", launch_node_mix(st, N, L, R, F->d_off, F->d_rpre, d_pdoff, Pd, 0, Y64, YP));
+  // dD = D^{-T} - Lam Y^T on the leaf blocks
+  HL("logdet_grad", launch_grad_leaf<S>(st, F->nleaf, F->m_max, F->d_off, R, Y64, N, Lam, N, dD, F->ldd, E64, N));
+  // projection trees V^T Y and U^T Lam (per node, all columns)
+  auto project = [&](const void* Mv, int64_t ldm, const double* Xin, double* tree) -> hodlr_status {
+    double* leaves = tree + tree_slot(L, 0) * (int64_t)R * R;
+    HL("logdet_grad", (launch_level_pass<double, double, S>(st, F->ntiles[L], F->d_tiles[L], F->tiles_aligned[L],
+                                                            const_cast<double*>(Xin), N, R, (const double*)nullptr, 0,
+                                                            0, (const double*)nullptr, 0, 0, 0,
+                                                            static_cast<const S*>(Mv), ldm, R, leaves)));
+    for (int l = L - 1; l >= 1; --l)
+      HL("logdet_grad", launch_tree_sum(st, 1 << l, (int64_t)R * R, tree + tree_slot(l + 1, 0) * (int64_t)R * R,
+                                        tree + tree_slot(l, 0) * (int64_t)R * R));
+    return HODLR_OK;
+  };
+  if ((s = project(F->V, F->ldv, Y64, tV))) return s;
+  if ((s = project(F->U, F->ldu, Lam, tU))) return s;
+  HL("logdet_grad", launch_grad_gen<S>(st, F->nleaf, L, F->d_off, F->d_rpre, R, R, Lam, N, tV, dU, F->ldu, Lam, N, 1));
+  HL("logdet_grad", launch_grad_gen<S>(st, F->nleaf, L, F->d_off, F->d_rpre, R, R, Y64, N, tU, dV, F->ldv, YP, N, 1));
+  return HODLR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+hodlr_status hodlr_logdet_grad(const hodlr_factors* Fc, void* dD, void* dU, void* dV, void* stream) {
+  hodlr_factors* F = const_cast<hodlr_factors*>(Fc);
+  if (!F || !dD || (F->R > 0 && (!dU || !dV))) return HODLR_ERR_ARG;
+  if (F->inplace) return HODLR_ERR_ARG;  // needs the original D, U, V
+  if (F->singular) return HODLR_ERR_SINGULAR;  // log|det A| is -inf: no gradient
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipStreamWaitEvent(st, F->ready, 0) != hipSuccess) return HODLR_ERR_HIP;
+  DevMem M;
+  hodlr_status s;
+  if (F->compute == HODLR_F64)
+    s = logdet_grad_impl<double, double>(F, st, M, dD, dU, dV);
+  else if (F->storage == HODLR_F64)
+    s = logdet_grad_impl<float, double>(F, st, M, dD, dU, dV);
+  else
+    s = logdet_grad_impl<float, float>(F, st, M, dD, dU, dV);
+  // the temporaries are released once the stream has used them
+  if (hipStreamSynchronize(st) != hipSuccess && s == HODLR_OK) s = HODLR_ERR_HIP;
+  M.release();
+  return s;
 }
 
 size_t hodlr_factor_bytes(const hodlr_factors* Fc) {

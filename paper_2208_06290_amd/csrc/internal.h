@@ -154,13 +154,18 @@ hipError_t launch_matvec_apply(hipStream_t s, int trans, int nleaf, int L, const
                                const int32_t* d_rpre, int R, const S* D, int64_t ldd, const S* Ua, int64_t lda,
                                const double* X, int64_t ldx, const double* tree, double* Y, int64_t ldy, int nrhs, int full);
 
-// Gradient pieces.
+// Gradient pieces.  grad_leaf: dD_a = add_a - Lam_a X_a^T on the leaf blocks (add may be null).
+// grad_gen: out(I_a, c) = add(I_a, c) - Left(I_a, :) S(c, :)^T with S the projection-tree entry of
+// the sibling of a's ancestor at c's level; tri = 1 restricts the sum to the columns of the
+// levels above c's level.
 template <typename S>
 hipError_t launch_grad_leaf(hipStream_t s, int nleaf, int m_max, const int64_t* d_leaf_off, int nrhs,
-                            const double* X, int64_t ldx, const double* Lam, int64_t ldl, S* dD, int64_t ldd);
+                            const double* X, int64_t ldx, const double* Lam, int64_t ldl, S* dD, int64_t ldd,
+                            const double* add = nullptr, int64_t ldadd = 0);
 template <typename S>
 hipError_t launch_grad_gen(hipStream_t s, int nleaf, int L, const int64_t* d_leaf_off, const int32_t* d_rpre, int R,
-                           int nrhs, const double* Left, int64_t ldl, const double* tree, S* out, int64_t ldo);
+                           int nrhs, const double* Left, int64_t ldl, const double* tree, S* out, int64_t ldo,
+                           const double* add = nullptr, int64_t ldadd = 0, int tri = 0);
 
 // Refinement helpers (FP64).
 hipError_t launch_colnorms(hipStream_t s, int64_t n, int nrhs, const double* X, int64_t ldx, double* part,
@@ -176,4 +181,39 @@ template <typename T, typename S>
 hipError_t launch_convert(hipStream_t s, int64_t rows, int cols, const S* in, int64_t ldi, T* out, int64_t ldo,
                           int64_t gsi = 256);
 
+}  // namespace hodlr
+
+namespace hodlr {
+// Coupling factors of the levels that have them, for the log-determinant:
+// per entry p < n, `count` parents of rank r, K stored with kp entries per
+// parent from element kvoff of the K vectors (interchanges, 1 / pivots).
+struct LogdetLevels {
+  int n = 0;
+  int count[HODLR_MAX_LEVELS];
+  int r[HODLR_MAX_LEVELS];
+  int kp[HODLR_MAX_LEVELS];
+  int64_t kvoff[HODLR_MAX_LEVELS];
+};
+// log|det A| (out[0]) and its sign (out[1]) from the leaf factors (1 / U_jj,
+// interchanges) and the coupling factors; item_log / item_par: nleaf + sum of
+// counts scratch entries.
+template <typename T>
+hipError_t launch_logdet(hipStream_t s, int nleaf, int ldl, const int64_t* d_leaf_off, const T* udinv,
+                         const int32_t* piv, const T* Kud, const int32_t* Kpiv, const LogdetLevels& lv,
+                         double* item_log, int* item_par, double* out);
+}  // namespace hodlr
+
+namespace hodlr {
+// Pieces of the gradient of log|det A| (logdet.hip).
+template <typename S>
+hipError_t launch_transpose_leaves(hipStream_t s, int nleaf, int m_max, const int64_t* d_leaf_off, const S* D,
+                                   int64_t ldd, S* Dt, int64_t ldt);
+template <typename T>
+hipError_t launch_identity_leaves(hipStream_t s, int nleaf, int ncols, const int64_t* d_leaf_off, T* E, int64_t lde);
+template <typename T>
+hipError_t launch_identity_blocks(hipStream_t s, int nblk, int n2, T* X);
+template <typename T>
+hipError_t launch_pblocks(hipStream_t s, int nparents, int r, const T* Kinv, int64_t ldk, int64_t pstride, double* Pd);
+hipError_t launch_node_mix(hipStream_t s, int64_t n, int L, int R, const int64_t* d_leaf_off, const int32_t* d_rpre,
+                           const int64_t* d_pdoff, const double* Pd, int trans, const double* in, double* out);
 }  // namespace hodlr

@@ -149,12 +149,14 @@ template hipError_t launch_matvec_apply<float>(hipStream_t, int, int, int, const
 // ---------------------------------------------------------------------------
 // gradients
 // ---------------------------------------------------------------------------
-// dD_a(i, j) = -sum_k Lam(o+i, k) X(o+j, k); WG = (leaf, 64-column chunk of the block)
+// dD_a(i, j) = add(o+i, j) - sum_k Lam(o+i, k) X(o+j, k) (add: FP64, ld ldadd, or null = 0);
+// WG = (leaf, 64-column chunk of the block)
 template <typename S>
 __global__ __launch_bounds__(kMvThreads) void grad_leaf_kernel(const int64_t* __restrict__ leaf_off, int nchunks,
                                                                int nrhs, const double* __restrict__ X, int64_t ldx,
                                                                const double* __restrict__ Lam, int64_t ldl,
-                                                               S* __restrict__ dD, int64_t ldd) {
+                                                               S* __restrict__ dD, int64_t ldd,
+                                                               const double* __restrict__ add, int64_t ldadd) {
   const int leaf = blockIdx.x / nchunks, ch = blockIdx.x % nchunks;
   const int64_t o = leaf_off[leaf];
   const int m = (int)(leaf_off[leaf + 1] - o);
@@ -193,31 +195,37 @@ __global__ __launch_bounds__(kMvThreads) void grad_leaf_kernel(const int64_t* __
       for (int t = 0; t < 4; ++t) {
         const int row = wr0 + 16 * rb + crow64(lq, t);
         const int col = c0 + 16 * cb + li;
-        if (row < m && col < m) dD[o + row + (int64_t)col * ldd] = (S)acc[rb][cb][t];
+        if (row < m && col < m)
+          dD[o + row + (int64_t)col * ldd] = (S)((add ? add[o + row + (int64_t)col * ldadd] : 0.0) + acc[rb][cb][t]);
       }
 }
 
 template <typename S>
 hipError_t launch_grad_leaf(hipStream_t s, int nleaf, int m_max, const int64_t* d_leaf_off, int nrhs,
-                            const double* X, int64_t ldx, const double* Lam, int64_t ldl, S* dD, int64_t ldd) {
+                            const double* X, int64_t ldx, const double* Lam, int64_t ldl, S* dD, int64_t ldd,
+                            const double* add, int64_t ldadd) {
   if (nleaf == 0) return hipSuccess;
   const int nchunks = (m_max + 63) / 64;
   hipLaunchKernelGGL(grad_leaf_kernel<S>, dim3((unsigned)(nleaf * nchunks)), dim3(kMvThreads), 0, s, d_leaf_off,
-                     nchunks, nrhs, X, ldx, Lam, ldl, dD, ldd);
+                     nchunks, nrhs, X, ldx, Lam, ldl, dD, ldd, add, ldadd);
   return hipGetLastError();
 }
 template hipError_t launch_grad_leaf<double>(hipStream_t, int, int, const int64_t*, int, const double*, int64_t,
-                                             const double*, int64_t, double*, int64_t);
+                                             const double*, int64_t, double*, int64_t, const double*, int64_t);
 template hipError_t launch_grad_leaf<float>(hipStream_t, int, int, const int64_t*, int, const double*, int64_t,
-                                            const double*, int64_t, float*, int64_t);
+                                            const double*, int64_t, float*, int64_t, const double*, int64_t);
 
-// out(I_leaf, c) = -sum_j Left(I_leaf, j) * S_l(c)[sib](c, j) for every column c of U_big / V_big
+// out(I_leaf, c) = add(I_leaf, c) - sum_j Left(I_leaf, j) * S_l(c)[sib](c, j) for every column c of
+// U_big / V_big (add: FP64 N x R with ld ldadd, or null = 0); the sum runs over j < nrhs, or with
+// tri = 1 over the columns of the levels above c's level only (j < R_{l-1})
 template <typename S>
 __global__ __launch_bounds__(kMvThreads) void grad_gen_kernel(const int64_t* __restrict__ leaf_off, int L,
                                                               const int32_t* __restrict__ rpre, int R, int nchunks,
                                                               int nrhs, const double* __restrict__ Left, int64_t ldl,
                                                               const double* __restrict__ tree,
-                                                              S* __restrict__ out, int64_t ldo) {
+                                                              S* __restrict__ out, int64_t ldo,
+                                                              const double* __restrict__ add, int64_t ldadd,
+                                                              int tri) {
   const int leaf = blockIdx.x / nchunks, ch = blockIdx.x % nchunks;
   const int64_t o = leaf_off[leaf];
   const int m = (int)(leaf_off[leaf + 1] - o);
@@ -226,7 +234,7 @@ __global__ __launch_bounds__(kMvThreads) void grad_gen_kernel(const int64_t* __r
   const int wr0 = 64 * w;
   // per column block cb: level, sibling block base
   const double* sb[4];
-  int cvalid[4];
+  int cvalid[4], klim[4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
     const int c = c0 + 16 * cb + li;
@@ -235,6 +243,7 @@ __global__ __launch_bounds__(kMvThreads) void grad_gen_kernel(const int64_t* __r
     while (l < L && c >= rpre[l]) ++l;
     const int node = leaf >> (L - l);
     sb[cb] = cvalid[cb] ? tree + tree_slot(l, node ^ 1) * R * nrhs + c : tree;
+    klim[cb] = tri ? min(nrhs, (int)rpre[l - 1]) : nrhs;
   }
   d4 acc[4][4];
 #pragma unroll
@@ -250,7 +259,7 @@ __global__ __launch_bounds__(kMvThreads) void grad_gen_kernel(const int64_t* __r
       av[rb] = (row < m && kk < nrhs) ? -Left[o + row + (int64_t)kk * ldl] : 0.0;
     }
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) bv[cb] = (cvalid[cb] && kk < nrhs) ? sb[cb][(int64_t)kk * R] : 0.0;
+    for (int cb = 0; cb < 4; ++cb) bv[cb] = (cvalid[cb] && kk < klim[cb]) ? sb[cb][(int64_t)kk * R] : 0.0;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
@@ -264,23 +273,27 @@ __global__ __launch_bounds__(kMvThreads) void grad_gen_kernel(const int64_t* __r
       for (int t = 0; t < 4; ++t) {
         const int row = wr0 + 16 * rb + crow64(lq, t);
         const int col = c0 + 16 * cb + li;
-        if (row < m && col < R) out[o + row + (int64_t)col * ldo] = (S)acc[rb][cb][t];
+        if (row < m && col < R)
+          out[o + row + (int64_t)col * ldo] = (S)((add ? add[o + row + (int64_t)col * ldadd] : 0.0) + acc[rb][cb][t]);
       }
 }
 
 template <typename S>
 hipError_t launch_grad_gen(hipStream_t s, int nleaf, int L, const int64_t* d_leaf_off, const int32_t* d_rpre, int R,
-                           int nrhs, const double* Left, int64_t ldl, const double* tree, S* out, int64_t ldo) {
+                           int nrhs, const double* Left, int64_t ldl, const double* tree, S* out, int64_t ldo,
+                           const double* add, int64_t ldadd, int tri) {
   if (nleaf == 0 || R == 0) return hipSuccess;
   const int nchunks = (R + 63) / 64;
   hipLaunchKernelGGL(grad_gen_kernel<S>, dim3((unsigned)(nleaf * nchunks)), dim3(kMvThreads), 0, s, d_leaf_off, L,
-                     d_rpre, R, nchunks, nrhs, Left, ldl, tree, out, ldo);
+                     d_rpre, R, nchunks, nrhs, Left, ldl, tree, out, ldo, add, ldadd, tri);
   return hipGetLastError();
 }
 template hipError_t launch_grad_gen<double>(hipStream_t, int, int, const int64_t*, const int32_t*, int, int,
-                                            const double*, int64_t, const double*, double*, int64_t);
+                                            const double*, int64_t, const double*, double*, int64_t, const double*,
+                                            int64_t, int);
 template hipError_t launch_grad_gen<float>(hipStream_t, int, int, const int64_t*, const int32_t*, int, int,
-                                           const double*, int64_t, const double*, float*, int64_t);
+                                           const double*, int64_t, const double*, float*, int64_t, const double*,
+                                           int64_t, int);
 
 // ---------------------------------------------------------------------------
 // refinement helpers (FP64)

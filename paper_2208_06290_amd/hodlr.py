@@ -55,8 +55,8 @@ class _Stats(ctypes.Structure):
 
 
 EXPORTS = ["hodlr_factor", "hodlr_refactor", "hodlr_solve", "hodlr_solve_adjoint", "hodlr_matvec", "hodlr_grad",
-           "hodlr_factors_y", "hodlr_factor_bytes", "hodlr_destroy", "hodlr_status_string",
-           "hodlr_timing_enable", "hodlr_kernel_times"]
+           "hodlr_logdet", "hodlr_logdet_grad", "hodlr_factors_y", "hodlr_factor_bytes", "hodlr_destroy",
+           "hodlr_status_string", "hodlr_timing_enable", "hodlr_kernel_times"]
 
 _lib = None
 
@@ -78,6 +78,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hodlr_matvec.argtypes = [ctypes.POINTER(_Matrix), i32, i64, vp, i64, vp, i64, vp]
     lib.hodlr_grad.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp, vp, vp]
     lib.hodlr_factors_y.argtypes = [vp, vp, i64, vp]
+    lib.hodlr_logdet.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
+    lib.hodlr_logdet_grad.argtypes = [vp, vp, vp, vp, vp]
     lib.hodlr_factor_bytes.argtypes = [vp]
     lib.hodlr_factor_bytes.restype = ctypes.c_size_t
     lib.hodlr_destroy.argtypes = [vp]
@@ -90,7 +92,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(ctypes.c_int64), i32]
     lib.hodlr_kernel_times.restype = i32
     for name in ("hodlr_factor", "hodlr_refactor", "hodlr_solve", "hodlr_solve_adjoint", "hodlr_matvec",
-                 "hodlr_grad", "hodlr_factors_y"):
+                 "hodlr_grad", "hodlr_logdet", "hodlr_logdet_grad", "hodlr_factors_y"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -241,6 +243,31 @@ class Factors:
         """lambda = A^{-T} g (FP64 result)."""
         return self._solve(load_library().hodlr_solve_adjoint, g, refine, tol, max_iter, stats, stream)
 
+    def slogdet(self):
+        """(sign, log|det A|) from the stored factors (sign 0 and -inf for an
+        exactly singular pivot)."""
+        lib = load_library()
+        sg, la = ctypes.c_double(), ctypes.c_double()
+        st = lib.hodlr_logdet(self._h, ctypes.byref(sg), ctypes.byref(la), _stream(self.A.device))
+        if st:
+            raise HodlrError(st, "hodlr_logdet")
+        return sg.value, la.value
+
+    def _grad_buffers(self):
+        # the library writes dD, dU, dV with the leading dimensions of D, U, V
+        A = self.A
+        return tuple(torch.empty_strided(t.shape, t.stride(), dtype=t.dtype, device=t.device).zero_()
+                     for t in (A.D, A.U, A.V))
+
+    def slogdet_grad(self):
+        """(dD, dU, dV) of log|det A| in the layouts and dtype of D, U, V."""
+        lib = load_library()
+        dD, dU, dV = self._grad_buffers()
+        st = lib.hodlr_logdet_grad(self._h, dD.data_ptr(), dU.data_ptr(), dV.data_ptr(), _stream(self.A.device))
+        if st:
+            raise HodlrError(st, "hodlr_logdet_grad")
+        return dD, dU, dV
+
     def y_big(self) -> torch.Tensor:
         """Y_big as an (R, N) float64 tensor (Y_a = A_a^{-1} U_a per level)."""
         lib = load_library()
@@ -257,10 +284,7 @@ class Factors:
         X, _ = _as_rhs(x, self.A.n)
         Lm, _ = _as_rhs(lam, self.A.n)
         A = self.A
-        # the library writes dD, dU, dV with the leading dimensions of D, U, V
-        dD = torch.empty_strided(A.D.shape, A.D.stride(), dtype=A.D.dtype, device=A.D.device).zero_()
-        dU = torch.empty_strided(A.U.shape, A.U.stride(), dtype=A.U.dtype, device=A.U.device).zero_()
-        dV = torch.empty_strided(A.V.shape, A.V.stride(), dtype=A.V.dtype, device=A.V.device).zero_()
+        dD, dU, dV = self._grad_buffers()
         st = lib.hodlr_grad(self._h, X.shape[0], X.data_ptr(), A.n, Lm.data_ptr(), A.n, dD.data_ptr(),
                             dU.data_ptr(), dV.data_ptr(), _stream(A.device))
         if st:
