@@ -181,6 +181,28 @@ hodlr_status hodlr_solve(const hodlr_factors *F, int64_t nrhs, double *B, int64_
 hodlr_status hodlr_solve_adjoint(const hodlr_factors *F, int64_t nrhs, double *B, int64_t ldb,
                                  const hodlr_solve_opts *opts, void *stream, hodlr_solve_stats *st);
 
+/* Allocation-free variant of hodlr_solve / hodlr_solve_adjoint without
+ * refinement, for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * B <- A^{-1} B (trans = 0) or A^{-T} B (trans = 1), B N x nrhs FP64,
+ * ldb >= N, in the factors' precision, with the same kernels and results as
+ * hodlr_solve / hodlr_solve_adjoint with refine = 0.  Instead of a per-stream
+ * workspace the call uses a fixed 64 MiB device scratch array that the
+ * library holds once per GPU until the process ends; it calls no hipMalloc,
+ * hipFree or allocating routine.  hodlr_solve_noalloc_bytes(F, nrhs) gives
+ * the scratch bytes a call needs; a call needing more than 64 MiB returns
+ * HODLR_ERR_ARG before launching anything (so does a call from a device
+ * other than the one F was factored on, which must be the current device).
+ * Every such call on one GPU shares that GPU's scratch, whose contents the
+ * last call leaves behind (nothing in it needs to start at zero): calls that
+ * may overlap on one GPU (other streams, other factorizations) race and must
+ * be ordered by the caller.  hodlr_refactor and hodlr_destroy wait for the
+ * last such call on F.  No refinement: its per-step convergence test
+ * synchronises the stream. */
+hodlr_status hodlr_solve_noalloc(const hodlr_factors *F, int32_t trans, int64_t nrhs, double *B,
+                                 int64_t ldb, void *stream);
+size_t hodlr_solve_noalloc_bytes(const hodlr_factors *F, int64_t nrhs);
+
 /* FP64 matrix product Y = A X (trans = 0) or Y = A^T X (trans = 1), reading
  * D, U, V in their storage type: y_a = D_a x_a + sum over levels of
  * U_a (V_b^T x_b) for the sibling b of each ancestor-or-self a (eq. "e:rank").

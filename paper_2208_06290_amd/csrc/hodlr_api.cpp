@@ -215,6 +215,11 @@ struct hodlr_factors {
   std::map<hipStream_t, std::unique_ptr<Workspace>> wsmap;
   hipEvent_t ready = nullptr;  // recorded after the factorization's last kernel
   bool singular = false;       // the last factorization met an exactly zero pivot
+  // allocation-free solves (hodlr_solve_noalloc): the device the factors live
+  // on, and the completion of the last such call (refactor and destroy wait on it)
+  int device = 0;
+  std::mutex na_mu;
+  hipEvent_t na_done = nullptr;
 };
 
 namespace {
@@ -457,6 +462,8 @@ hodlr_status allocate_factors(hodlr_factors* F) {
   F->segbuf = b;
   if ((s = M.alloc(&F->d_info, 2))) return s;
   if (hipEventCreateWithFlags(&F->ready, hipEventDisableTiming) != hipSuccess) return HODLR_ERR_HIP;
+  if (hipEventCreateWithFlags(&F->na_done, hipEventDisableTiming) != hipSuccess) return HODLR_ERR_HIP;
+  if (hipGetDevice(&F->device) != hipSuccess) return HODLR_ERR_HIP;
   return HODLR_OK;
 }
 
@@ -615,6 +622,16 @@ WsSizes ws_sizes(const hodlr_factors* F, int nrhs) {
     if (F->ranks[p] > 0) items += (size_t)1 << p;
   z.ld = 2 * items + 8;  // doubles: logs, then parities (ints) in the second half, then the result
   return z;
+}
+
+// Scratch bytes of an unrefined solve with nrhs columns (tile partials, segment
+// sums, W, and the compute-type copy of B for FP32 factors), each buffer
+// aligned to 256 bytes.
+size_t noalloc_bytes(const hodlr_factors* F, int nrhs) {
+  const WsSizes z = ws_sizes(F, nrhs);
+  const size_t ts = F->tsize;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return al(z.pmax * ts) + al(z.segmax * ts) + al(z.wmax * ts) + (ts == 8 ? 0 : al(z.n * ts));
 }
 
 hodlr_status ensure_ws(hodlr_factors* F, Workspace& W, int nrhs) {
@@ -925,6 +942,7 @@ hodlr_status hodlr_factor(const hodlr_matrix* A, hodlr_dtype compute, int32_t fl
   if (s != HODLR_OK) {
     F->mem.release();
     if (F->ready) hipEventDestroy(F->ready);
+    if (F->na_done) hipEventDestroy(F->na_done);
     delete F;
     return s;
   }
@@ -936,6 +954,7 @@ hodlr_status hodlr_factor(const hodlr_matrix* A, hodlr_dtype compute, int32_t fl
     hipStreamSynchronize(st);
     F->mem.release();
     hipEventDestroy(F->ready);
+    hipEventDestroy(F->na_done);
     delete F;
     return s;
   }
@@ -962,6 +981,8 @@ hodlr_status hodlr_refactor(hodlr_factors* F, const hodlr_matrix* A, void* strea
     held.emplace_back(kv.second->mu);
     if (hipStreamWaitEvent(st, kv.second->done, 0) != hipSuccess) return HODLR_ERR_HIP;
   }
+  std::lock_guard<std::mutex> gna(F->na_mu);
+  if (hipStreamWaitEvent(st, F->na_done, 0) != hipSuccess) return HODLR_ERR_HIP;
   F->D = A->D;
   F->U = A->U;
   F->V = A->V;
@@ -983,6 +1004,48 @@ hodlr_status hodlr_solve(const hodlr_factors* F, int64_t nrhs, double* B, int64_
 hodlr_status hodlr_solve_adjoint(const hodlr_factors* F, int64_t nrhs, double* B, int64_t ldb,
                                  const hodlr_solve_opts* o, void* stream, hodlr_solve_stats* st) {
   return solve_common(F, 1, nrhs, B, ldb, o, stream, st);
+}
+
+size_t hodlr_solve_noalloc_bytes(const hodlr_factors* F, int64_t nrhs) {
+  if (!F || nrhs < 0 || nrhs > 65535) return 0;
+  return noalloc_bytes(F, (int)nrhs);
+}
+
+hodlr_status hodlr_solve_noalloc(const hodlr_factors* Fc, int32_t trans, int64_t nrhs, double* B, int64_t ldb,
+                                 void* stream) {
+  hodlr_factors* F = const_cast<hodlr_factors*>(Fc);
+  if (!F || (trans != 0 && trans != 1) || nrhs < 0 || nrhs > 65535 || (nrhs > 0 && (!B || ldb < F->n)))
+    return HODLR_ERR_ARG;
+  if (nrhs == 0) return HODLR_OK;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return HODLR_ERR_HIP;
+  if (dev != F->device) return HODLR_ERR_ARG;
+  const size_t need = noalloc_bytes(F, (int)nrhs);
+  if (need > scratch_capacity()) return HODLR_ERR_ARG;
+  void* base = nullptr;
+  if (scratch_device_ptr(&base) != hipSuccess) return HODLR_ERR_HIP;
+  // the solve-side buffers carved out of this device's scratch (every byte
+  // the solve reads there is written earlier in the same call)
+  Workspace W;
+  unsigned char* p = static_cast<unsigned char*>(base);
+  const WsSizes z = ws_sizes(F, (int)nrhs);
+  const size_t ts = F->tsize;
+  auto take = [&](size_t bytes) {
+    void* q = p;
+    p += (bytes + 255) & ~size_t(255);
+    return q;
+  };
+  W.sP = take(z.pmax * ts);
+  W.sseg = take(z.segmax * ts);
+  W.sw = take(z.wmax * ts);
+  W.sx = ts == 8 ? nullptr : take(z.n * ts);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> g(F->na_mu);
+  if (hipStreamWaitEvent(st, F->ready, 0) != hipSuccess) return HODLR_ERR_HIP;
+  hodlr_status s = F->compute == HODLR_F64 ? solve_impl<double>(F, W, trans, (int)nrhs, B, ldb, nullptr, st, nullptr)
+                                           : solve_impl<float>(F, W, trans, (int)nrhs, B, ldb, nullptr, st, nullptr);
+  if (hipEventRecord(F->na_done, st) != hipSuccess && s >= 0) s = HODLR_ERR_HIP;
+  return s;
 }
 
 hodlr_status hodlr_matvec(const hodlr_matrix* A, int32_t trans, int64_t nrhs, const double* X, int64_t ldx, double* Yo,
@@ -1282,6 +1345,7 @@ void hodlr_destroy(hodlr_factors* F) {
   // wait only for this factorization's own work: the factorization itself and
   // the last call on each stream that used it
   hipEventSynchronize(F->ready);
+  hipEventSynchronize(F->na_done);
   for (auto& kv : F->wsmap) {
     hipEventSynchronize(kv.second->done);
     kv.second->mem.release();
@@ -1290,6 +1354,7 @@ void hodlr_destroy(hodlr_factors* F) {
   F->wsmap.clear();
   F->mem.release();
   hipEventDestroy(F->ready);
+  hipEventDestroy(F->na_done);
   delete F;
 }
 

@@ -184,6 +184,14 @@ hipError_t launch_convert(hipStream_t s, int64_t rows, int cols, const S* in, in
 }  // namespace hodlr
 
 namespace hodlr {
+// Fixed device scratch of the allocation-free solve (noalloc.hip): capacity in
+// bytes, and this device's address of it (the current device; looked up once
+// per device).
+size_t scratch_capacity();
+hipError_t scratch_device_ptr(void** out);
+}  // namespace hodlr
+
+namespace hodlr {
 // Coupling factors of the levels that have them, for the log-determinant:
 // per entry p < n, `count` parents of rank r, K stored with kp entries per
 // parent from element kvoff of the K vectors (interchanges, 1 / pivots).

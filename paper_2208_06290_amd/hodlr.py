@@ -54,9 +54,10 @@ class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("relres", ctypes.c_double)]
 
 
-EXPORTS = ["hodlr_factor", "hodlr_refactor", "hodlr_solve", "hodlr_solve_adjoint", "hodlr_matvec", "hodlr_grad",
-           "hodlr_logdet", "hodlr_logdet_grad", "hodlr_factors_y", "hodlr_factor_bytes", "hodlr_destroy",
-           "hodlr_status_string", "hodlr_timing_enable", "hodlr_kernel_times"]
+EXPORTS = ["hodlr_factor", "hodlr_refactor", "hodlr_solve", "hodlr_solve_adjoint", "hodlr_solve_noalloc",
+           "hodlr_solve_noalloc_bytes", "hodlr_matvec", "hodlr_grad", "hodlr_logdet", "hodlr_logdet_grad",
+           "hodlr_factors_y", "hodlr_factor_bytes", "hodlr_destroy", "hodlr_status_string", "hodlr_timing_enable",
+           "hodlr_kernel_times"]
 
 _lib = None
 
@@ -75,6 +76,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hodlr_refactor.argtypes = [vp, ctypes.POINTER(_Matrix), vp, ctypes.POINTER(_Info)]
     for f in (lib.hodlr_solve, lib.hodlr_solve_adjoint):
         f.argtypes = [vp, i64, vp, i64, ctypes.POINTER(_Opts), vp, ctypes.POINTER(_Stats)]
+    lib.hodlr_solve_noalloc.argtypes = [vp, i32, i64, vp, i64, vp]
+    lib.hodlr_solve_noalloc_bytes.argtypes = [vp, i64]
+    lib.hodlr_solve_noalloc_bytes.restype = ctypes.c_size_t
     lib.hodlr_matvec.argtypes = [ctypes.POINTER(_Matrix), i32, i64, vp, i64, vp, i64, vp]
     lib.hodlr_grad.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp, vp, vp]
     lib.hodlr_factors_y.argtypes = [vp, vp, i64, vp]
@@ -91,8 +95,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hodlr_kernel_times.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64), i32]
     lib.hodlr_kernel_times.restype = i32
-    for name in ("hodlr_factor", "hodlr_refactor", "hodlr_solve", "hodlr_solve_adjoint", "hodlr_matvec",
-                 "hodlr_grad", "hodlr_logdet", "hodlr_logdet_grad", "hodlr_factors_y"):
+    for name in ("hodlr_factor", "hodlr_refactor", "hodlr_solve", "hodlr_solve_adjoint", "hodlr_solve_noalloc",
+                 "hodlr_matvec", "hodlr_grad", "hodlr_logdet", "hodlr_logdet_grad", "hodlr_factors_y"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -242,6 +246,23 @@ class Factors:
                       stats: Optional[dict] = None, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
         """lambda = A^{-T} g (FP64 result)."""
         return self._solve(load_library().hodlr_solve_adjoint, g, refine, tol, max_iter, stats, stream)
+
+    def solve_noalloc_(self, B: torch.Tensor, adjoint: bool = False) -> torch.Tensor:
+        """In place B <- A^{-1} B (or A^{-T} B) through the allocation-free entry
+        point: B must be a contiguous (nrhs, N) or (N,) float64 device tensor
+        (it is overwritten and returned); no refinement."""
+        lib = load_library()
+        _check_dev(B, "right-hand side")
+        if B.dtype != torch.float64 or not B.is_contiguous() or B.shape[-1] != self.A.n or B.dim() > 2:
+            raise ValueError("B must be a contiguous float64 (nrhs, N) or (N,) tensor")
+        nrhs = 1 if B.dim() == 1 else B.shape[0]
+        st = lib.hodlr_solve_noalloc(self._h, int(adjoint), nrhs, B.data_ptr(), self.A.n, _stream(self.A.device))
+        if st:
+            raise HodlrError(st, "hodlr_solve_noalloc")
+        return B
+
+    def noalloc_bytes(self, nrhs: int) -> int:
+        return int(load_library().hodlr_solve_noalloc_bytes(self._h, nrhs))
 
     def slogdet(self):
         """(sign, log|det A|) from the stored factors (sign 0 and -inf for an
