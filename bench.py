@@ -34,10 +34,11 @@ PEAK = dict(hbm=8.0e12, f64=78.6e12, f32=157.3e12, bf16=2.5e15)
 # HBM traffic of the level pass per launch (one tree level) of the FP64
 # factorization at N = 2^20, leaf 256, rank 32, from two rocprofv3 counter runs
 # (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, the factors that a plain 1 GiB copy
-# reads back; summary and commands in profiles/level_pass_traffic_n1m_fp64.md).
+# reads back; summary and commands in profiles/level_pass_traffic_n1m_fp64.md
+# and profiles/counters_n1m_synthetic_fp64_fp32_bf16.md).
 # It is reported only while the kernel source is the one it was measured on.
 LEVEL_PASS_TRAFFIC = dict(
-    source_sha256="fdc30a8fc87fa87d5814ea80c0f1fb9946f9b6c3ba356b3ab3e5f18e505f7208",
+    source_sha256="b27927773f753f35361de738cd42de469df5a5011658928c1acc1e600e7a87e2",
     n=1 << 20, leaf=256, rank=32, bytes_per_launch=4.26e9)
 
 
