@@ -27,8 +27,16 @@ namespace hodlr {
 
 constexpr int kTwLd = 17;  // padded row length of the owner's 16 x 16 turn-around buffer
 
+// Resident workgroups per CU: four waves with accumulators of at most 64
+// registers per lane (4 blocks x 2 column blocks of FP64, or 4 x 4 of FP32)
+// keep four workgroups per CU, wider chunks two; eight waves two, or one.
+template <typename T, int NW, int NQ, int NCB>
+constexpr int trsm_occupancy() {
+  return NW == 4 ? (NQ * NCB * (int)sizeof(T) <= 64 ? 4 : 2) : (NCB <= 2 ? 2 : 1);
+}
+
 template <typename T, typename S, int TRANS, int NW, int NQ, int NCB, bool BF>
-__global__ __launch_bounds__(64 * NW, NW == 4 ? (NCB <= 2 ? 4 : 2) : (NCB <= 2 ? 2 : 1)) void trsm_kernel(int ldl, const int64_t* __restrict__ leaf_off,
+__global__ __launch_bounds__(64 * NW, (trsm_occupancy<T, NW, NQ, NCB>())) void trsm_kernel(int ldl, const int64_t* __restrict__ leaf_off,
                                                              int64_t ostride, int mfix, const T* lu, int64_t lul,
                                                              int inplace, const int32_t* __restrict__ perm,
                                                              const T* __restrict__ dinv, const S* B, int64_t ldb,
@@ -225,7 +233,11 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
   // chunks of 128 columns for few blocks and of 64 (twice the workgroups per
   // CU) for many; otherwise four blocks per wave and 32 columns
   const int nq = ldl <= 64 ? 1 : 4;
-  const int cw = nq == 1 ? (ncols > 64 && nblk < 512 ? 128 : ncols > 16 ? 64 : 16) : (ncols > 16 ? 32 : 16);
+  // 4-byte elements: 64-column chunks of the leaf blocks hold as many
+  // accumulator registers as 32 FP64 columns (four workgroups per CU), with
+  // half the chunks and half the re-reads of each leaf's factors
+  const int wide = sizeof(T) == 4 && nq == 4 && ncols > 32 ? 64 : 32;
+  const int cw = nq == 1 ? (ncols > 64 && nblk < 512 ? 128 : ncols > 16 ? 64 : 16) : (ncols > 16 ? wide : 16);
   const int nchunks = (ncols + cw - 1) / cw;
   const int64_t grid = (int64_t)nblk * nchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
@@ -233,6 +245,11 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
   hipLaunchKernelGGL((trsm_kernel<T, S, TR, NW, NQ, NC, BFV>), dim3((unsigned)grid), dim3(64 * NW), 0, s, ldl, d_off, \
                      ostride, mfix, lu, lul, inplace, perm, dinv, B, ldb, X, ldx, ncols, nchunks, gsb, gsx)
 #define HODLR_TS(TR, NW, NQ, NC) HODLR_TS_B(TR, NW, NQ, NC, false)
+  // the 64-column leaf instance exists for 4-byte elements only
+#define HODLR_TS_64(TR)                                \
+  do {                                                 \
+    if constexpr (sizeof(T) == 4) HODLR_TS(TR, 4, 4, 4); \
+  } while (0)
   // up to 64 rows: 4 waves, one block each; up to 256 rows: 4 waves with four
   // blocks each for wide right-hand sides, 8 waves with two each for narrow ones
 #define HODLR_TS_W(TR)                         \
@@ -241,7 +258,8 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
     else if (cw == 64) HODLR_TS(TR, 4, 1, 4);  \
     else HODLR_TS(TR, 4, 1, 1);                \
   } else {                                     \
-    if (cw == 32) HODLR_TS(TR, 4, 4, 2);       \
+    if (cw == 64) HODLR_TS_64(TR);             \
+    else if (cw == 32) HODLR_TS(TR, 4, 4, 2);  \
     else HODLR_TS(TR, 8, 2, 1);                \
   }
   // bfloat16 operands (FP32 factors and accumulation): the leaf solve of a
@@ -249,7 +267,8 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
   bool done = false;
   if constexpr (sizeof(T) == 4) {
     if (bf && !trans && nq == 4) {
-      if (cw == 32) HODLR_TS_B(0, 4, 4, 2, true);
+      if (cw == 64) HODLR_TS_B(0, 4, 4, 4, true);
+      else if (cw == 32) HODLR_TS_B(0, 4, 4, 2, true);
       else HODLR_TS_B(0, 8, 2, 1, true);
       done = true;
     }
@@ -261,6 +280,7 @@ static hipError_t launch_trsm(hipStream_t s, int trans, int nblk, int ldl, const
     HODLR_TS_W(0)
   }
 #undef HODLR_TS_W
+#undef HODLR_TS_64
 #undef HODLR_TS
 #undef HODLR_TS_B
   return hipGetLastError();
