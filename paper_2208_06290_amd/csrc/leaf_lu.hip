@@ -16,8 +16,9 @@
 //      LDS and every thread selects the winner, one barrier per column.
 // Entries are stored by original row while factoring (later interchanges move
 // no data); a final pass writes them in pivoted order.  Four workgroups per CU
-// (the panel steps are latency-bound): at most 128 registers per lane and
-// 40 KB of LDS, so the panel rows reach the registers 8 columns at a time
+// in FP64, five with 4-byte elements (the panel steps are latency-bound): at
+// most 128 registers per lane and 40 KB of LDS, so the panel rows reach the
+// registers 8 columns at a time
 // and the diagonal-block inverses are formed with rolled loops, their
 // columns in LDS.
 //
@@ -41,7 +42,7 @@ constexpr int kLuThreads = 256;
 constexpr int kCW = 32;  // chunk (panel) width
 
 template <typename T, typename S, int CW, bool BF>
-__global__ __launch_bounds__(kLuThreads, 4) void leaf_lu_kernel(int ldl, const int64_t* __restrict__ leaf_off,
+__global__ __launch_bounds__(kLuThreads, sizeof(T) == 4 ? 5 : 4) void leaf_lu_kernel(int ldl, const int64_t* __restrict__ leaf_off,
                                                              const S* D, int64_t ldd, T* lu, int64_t lul,
                                                              int inplace, int32_t* __restrict__ piv,
                                                              int32_t* __restrict__ perm,
