@@ -37,6 +37,7 @@ CASES = {
     "ragged_L6": dict(n=3001, L=6, ranks=[33, 20, 64, 9, 1, 17]),                # LU route, mixed
     "ragged_L4_r0": dict(n=1000, L=4, ranks=[7, 0, 13, 5]),                      # a rank-0 level
     "deep_L8": dict(n=4096, leaf=16, ranks=[4, 8, 3, 5, 6, 2, 7, 3]),
+    "leaf256_L5_mixed": dict(n=8192, leaf=256, ranks=[16, 48, 32, 32, 32]),      # fused bottom levels
     "L0_leaf200": dict(n=200, leaf=200, ranks=[]),
 }
 

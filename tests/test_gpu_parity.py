@@ -80,6 +80,7 @@ CASES = {
     "ragged_L4": dict(n=1000, leaf=None, L=4, ranks=[7, 0, 13, 5]),
     "ragged_L6": dict(n=3001, leaf=None, L=6, ranks=[33, 20, 64, 9, 1, 17]),
     "leaf256_L3": dict(n=2048, leaf=256, ranks=[32, 32, 32]),
+    "leaf256_L5_mixed": dict(n=8192, leaf=256, ranks=[16, 48, 32, 32, 32]),
     "leaf128_L5_r64": dict(n=4096, leaf=128, ranks=64),
     "deep_L8": dict(n=4096, leaf=16, ranks=[4, 8, 3, 5, 6, 2, 7, 3]),
 }
@@ -104,7 +105,8 @@ def test_fp64_solve_matches_oracle(name, nrhs):
     assert _rel(X, Xo) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["cfg0_like", "ragged_L6", "leaf128_L5_r64", "deep_L8"])
+@pytest.mark.parametrize("name", ["cfg0_like", "ragged_L6", "leaf128_L5_r64", "deep_L8", "leaf256_L3",
+                                  "leaf256_L5_mixed"])
 def test_Y_big_matches_oracle(name):
     _say(f"Y case {name}")
     inp, H, A = _build(name, seed=2)
@@ -211,7 +213,8 @@ def test_autograd_function_matches_oracle(variant):
     assert max(errs.values()) < tol, errs
 
 
-CASES_FP32 = ["cfg0_like", "L1_r10", "ragged_L4", "ragged_L6", "deep_L8", "leaf128_L5_r64", "leaf256_L3"]
+CASES_FP32 = ["cfg0_like", "L1_r10", "ragged_L4", "ragged_L6", "deep_L8", "leaf128_L5_r64", "leaf256_L3",
+              "leaf256_L5_mixed"]
 
 
 @pytest.mark.parametrize("storage", [torch.float64, torch.float32])
