@@ -25,3 +25,4 @@ from .hodlr_oracle import (  # noqa: F401
     relres,
 )
 from .extended_sparse import extended_sparse_solve  # noqa: F401
+from .construct import KernelSpec, entries as kernel_entries, aca, build as construct_hodlr, dense as kernel_dense  # noqa: F401

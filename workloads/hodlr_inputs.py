@@ -185,6 +185,14 @@ def _star_geometry(n: int, device, amp=0.3, k=5):
     return x, y, nx, ny, kappa, w
 
 
+def star_curve(n: int, device="cpu") -> dict:
+    """The star curve's trapezoid nodes (geometry only): ``points`` (n, 2),
+    inward unit ``normals`` (n, 2), quadrature ``weights`` (n,) and
+    ``curvature`` (n,), float64 tensors."""
+    x, y, nx, ny, kappa, w = _star_geometry(n, device)
+    return dict(points=torch.stack([x, y], 1), normals=torch.stack([nx, ny], 1), weights=w, curvature=kappa)
+
+
 class _BieEntries:
     """A_ij = 1/2 delta_ij + w_j d(x_i, x_j), d(x,y) = n(y).(x-y) / (2 pi |x-y|^2)
     with the inward normal; the diagonal uses the smooth limit kappa/(4 pi)."""
@@ -326,6 +334,14 @@ def rcb_order(P: np.ndarray, leaf: int) -> np.ndarray:
     return np.concatenate(out)
 
 
+def kernel_points(n: int, dim: int, leaf: int, seed: int = 0) -> np.ndarray:
+    """n points uniform in [0,1]^dim (seeded), in RCB order with ``leaf``-point
+    leaves: an (n, dim) float64 array."""
+    rng = np.random.default_rng(int(seed) * 7919 + 17)
+    pts = rng.random((n, dim))
+    return pts[rcb_order(pts, leaf)]
+
+
 def _kernel_fn(kind: str):
     if kind == "gauss":
         s2 = 2.0 * 0.05 ** 2
@@ -368,10 +384,7 @@ def kernel_matrix(n: int, leaf: int, rank: int, kind: str, dim: int, nugget: flo
     per node."""
     levels = int(round(math.log2(n // leaf)))
     offsets = uniform_offsets(n, levels)
-    rng = np.random.default_rng(int(seed) * 7919 + 17)
-    pts = rng.random((n, dim))
-    pts = pts[rcb_order(pts, leaf)]
-    P = torch.as_tensor(pts, dtype=torch.float64, device=device)
+    P = torch.as_tensor(kernel_points(n, dim, leaf, seed), dtype=torch.float64, device=device)
     f = _kernel_fn(kind)
     nl = 1 << levels
     idx = torch.arange(n, device=device).view(nl, leaf)
