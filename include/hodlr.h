@@ -260,6 +260,61 @@ hodlr_status hodlr_logdet(const hodlr_factors *F, double *sign, double *logabs, 
  * synchronises `stream` before freeing them. */
 hodlr_status hodlr_logdet_grad(const hodlr_factors *F, void *dD, void *dU, void *dV, void *stream);
 
+/* Kernel matrices that hodlr_construct compresses.  Entry A(p, q), p != q:
+ *   HODLR_KERNEL_GAUSS       exp(-|x_p - x_q|^2 / (2 ell^2))          (Section I,
+ *   HODLR_KERNEL_MATERN32    (1 + s) exp(-s), s = sqrt(3) |x_p - x_q| / ell
+ *                            "Kernel matrices": Gaussian and Matern kernels)
+ *   HODLR_KERNEL_LAPLACE_DL  w_q n_q . (x_p - x_q) / (2 pi |x_p - x_q|^2)
+ *                            (Section IV-B, the double-layer kernel d(x, y) of
+ *                            eq. "e:laplace_int" with trapezoidal weights w_q
+ *                            and unit normals n_q of a closed curve in 2-D)
+ * Diagonal A(p, p): 1 (radial kernels) or the smooth limit w_p kappa_p / (4 pi)
+ * (double layer, kappa the signed curvature), plus `shift` (a nugget, or 1/2
+ * for the second-kind equation).
+ *   points     device, N x dim FP64, column-major with ld ldp (dim 1..3 for the
+ *              radial kernels, 2 for the double layer)
+ *   normals    LAPLACE_DL: device, N x 2 FP64 with ld ldp; else ignored
+ *   weights, curvature   LAPLACE_DL: device, N FP64 each; else ignored
+ *   ell        length scale of the radial kernels, > 0
+ */
+typedef enum {
+  HODLR_KERNEL_GAUSS = 0,
+  HODLR_KERNEL_MATERN32 = 1,
+  HODLR_KERNEL_LAPLACE_DL = 2
+} hodlr_kernel_kind;
+
+typedef struct {
+  hodlr_kernel_kind kind;
+  int32_t dim;
+  const double *points;
+  int64_t ldp;
+  const double *normals;
+  const double *weights;
+  const double *curvature;
+  double ell;
+  double shift;
+} hodlr_kernel;
+
+/* Construction of a HODLR approximation of the kernel matrix of `k`
+ * (Section II-B: every sibling block compressed on its own; Section IV-A
+ * compresses them by an approximate partial-pivoted LU).  The leaf blocks
+ * are exact; every sibling block A(I_a, I_b) of level l is approximated by
+ * r_l steps of cross approximation with partial pivoting:
+ *   v = A(i_k, :) - sum_{l<k} u_l(i_k) v_l,  j_k = argmax |v|,  v_k = v / v(j_k),
+ *   u_k = A(:, j_k) - sum_{l<k} v_l(j_k) u_l,  i_{k+1} = argmax over unused rows |u_k|,
+ * i_1 the block's first row, ties to the lowest index, an exhausted step
+ * (v(j_k) = 0) giving u_k = v_k = 0; U_a = [u_1..u_r] and V_b = [v_1..v_r].
+ * The tree, ranks and outputs are described as in hodlr_matrix: n, levels,
+ * leaf_offsets (host, NULL = uniform), ranks (host), dtype (F64 or F32
+ * storage of the outputs), D (N x m_max, ld ldd; entries right of a leaf's
+ * width set to zero), U, V (N x R, ld ldu / ldv; every entry written).
+ * Arithmetic is FP64 throughout; F32 outputs are rounded once at the end.
+ * N < 2^31.  Allocates temporaries (pivot bookkeeping; FP64 copies of U, V
+ * for F32 outputs) and synchronises `stream` before freeing them. */
+hodlr_status hodlr_construct(const hodlr_kernel *k, int64_t n, int32_t levels, const int64_t *leaf_offsets,
+                             const int32_t *ranks, hodlr_dtype dtype, void *D, int64_t ldd, void *U,
+                             int64_t ldu, void *V, int64_t ldv, void *stream);
+
 /* Device bytes owned by F: the factors, the factorization's workspace and
  * the solve workspaces of every stream F was used on. */
 size_t hodlr_factor_bytes(const hodlr_factors *F);

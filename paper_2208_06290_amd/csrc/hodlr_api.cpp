@@ -1396,3 +1396,113 @@ int32_t hodlr_kernel_times(const char** names, double* total_ms, int64_t* launch
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// construction by cross approximation
+// ---------------------------------------------------------------------------
+extern "C" {
+
+hodlr_status hodlr_construct(const hodlr_kernel* k, int64_t n, int32_t levels, const int64_t* leaf_offsets,
+                             const int32_t* ranks, hodlr_dtype dtype, void* D, int64_t ldd, void* U, int64_t ldu,
+                             void* V, int64_t ldv, void* stream) {
+  if (!k || !k->points) return HODLR_ERR_ARG;
+  if (k->kind == HODLR_KERNEL_LAPLACE_DL) {
+    if (k->dim != 2 || !k->normals || !k->weights || !k->curvature) return HODLR_ERR_ARG;
+  } else if (k->kind == HODLR_KERNEL_GAUSS || k->kind == HODLR_KERNEL_MATERN32) {
+    if (k->dim < 1 || k->dim > 3 || !(k->ell > 0.0) || !std::isfinite(k->ell)) return HODLR_ERR_ARG;
+  } else {
+    return HODLR_ERR_ARG;
+  }
+  if (k->ldp < n || !std::isfinite(k->shift)) return HODLR_ERR_ARG;
+  if (n >= (int64_t(1) << 31)) return HODLR_ERR_UNSUPPORTED;
+  hodlr_matrix A{n, levels, leaf_offsets, ranks, dtype, D, ldd, U, ldu, V, ldv};
+  std::vector<int64_t> off;
+  std::vector<int> rk;
+  int m_max = 0;
+  hodlr_status s = validate(&A, off, rk, m_max);
+  if (s) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int L = levels;
+  int R = 0, kmax = 0;
+  for (int r : rk) {
+    R += r;
+    kmax = std::max(kmax, r);
+  }
+  hodlr::ConstructKernel kd{(int)k->kind, k->dim, k->points, k->ldp, k->normals, k->weights, k->curvature, k->ell,
+                            k->shift};
+  DevMem M;
+  auto run = [&]() -> hodlr_status {
+    hodlr_status e;
+    int64_t* d_off = nullptr;
+    if ((e = M.alloc(&d_off, off.size()))) return e;
+    if (hipMemcpyAsync(d_off, off.data(), off.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+      return HODLR_ERR_HIP;
+    const int nleaf = 1 << L;
+    if (dtype == HODLR_F64)
+      HL("construct_leaves",
+         hodlr::launch_construct_leaves<double>(st, kd, nleaf, d_off, m_max, static_cast<double*>(D), ldd));
+    else
+      HL("construct_leaves",
+         hodlr::launch_construct_leaves<float>(st, kd, nleaf, d_off, m_max, static_cast<float*>(D), ldd));
+    if (R == 0) return HODLR_OK;
+    // the sibling blocks of every level and their tiles
+    const int te = hodlr::aca_tile_elems();
+    std::vector<hodlr::AcaBlock> blocks;
+    std::vector<hodlr::AcaTile> tiles;
+    int col = 0;
+    for (int l = 1; l <= L; ++l) {
+      const int r = rk[l - 1];
+      if (r > 0) {
+        const int per = 1 << (L - l);
+        for (int a = 0; a < (1 << l); ++a) {
+          const int b = a ^ 1;
+          hodlr::AcaBlock B;
+          B.r0 = off[(size_t)a * per];
+          B.m = (int32_t)(off[(size_t)(a + 1) * per] - B.r0);
+          B.c0 = off[(size_t)b * per];
+          B.n = (int32_t)(off[(size_t)(b + 1) * per] - B.c0);
+          B.col = col;
+          B.rank = r;
+          B.tile0 = (int32_t)tiles.size();
+          B.ntile = (std::max(B.m, B.n) + te - 1) / te;
+          for (int t = 0; t < B.ntile; ++t) tiles.push_back({(int32_t)blocks.size(), t, (int32_t)tiles.size()});
+          blocks.push_back(B);
+        }
+      }
+      col += r;
+    }
+    const size_t nt = tiles.size();
+    hodlr::AcaBlock* d_blocks = nullptr;
+    hodlr::AcaTile* d_tiles = nullptr;
+    hodlr::AcaPartials P{};
+    if ((e = M.alloc(&d_blocks, blocks.size())) || (e = M.alloc(&d_tiles, nt)) || (e = M.alloc(&P.rp_abs, nt)) ||
+        (e = M.alloc(&P.rp_val, nt)) || (e = M.alloc(&P.rp_idx, nt)) || (e = M.alloc(&P.cp_abs, nt)) ||
+        (e = M.alloc(&P.cp_idx, nt)) || (e = M.alloc(&P.piv, blocks.size() * kmax)))
+      return e;
+    if (hipMemcpyAsync(d_blocks, blocks.data(), blocks.size() * sizeof(hodlr::AcaBlock), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(d_tiles, tiles.data(), nt * sizeof(hodlr::AcaTile), hipMemcpyHostToDevice, st) != hipSuccess)
+      return HODLR_ERR_HIP;
+    double* U64 = static_cast<double*>(U);
+    double* V64 = static_cast<double*>(V);
+    int64_t ldu64 = ldu, ldv64 = ldv;
+    if (dtype == HODLR_F32) {
+      if ((e = M.alloc(&U64, (size_t)n * R)) || (e = M.alloc(&V64, (size_t)n * R))) return e;
+      ldu64 = ldv64 = n;
+    }
+    for (int step = 0; step < kmax; ++step)
+      HL("aca_step", hodlr::launch_aca_step(st, kd, (int)nt, d_blocks, d_tiles, step, kmax, U64, ldu64, V64, ldv64, P));
+    if (dtype == HODLR_F32) {
+      HL("construct_store", hodlr::launch_store_cols<float>(st, n, R, U64, ldu64, static_cast<float*>(U), ldu));
+      HL("construct_store", hodlr::launch_store_cols<float>(st, n, R, V64, ldv64, static_cast<float*>(V), ldv));
+    }
+    return HODLR_OK;
+  };
+  s = run();
+  // the host vectors the copies read and the temporaries live until the stream is done
+  if (hipStreamSynchronize(st) != hipSuccess && s == HODLR_OK) s = HODLR_ERR_HIP;
+  M.release();
+  return s;
+}
+
+}  // extern "C"

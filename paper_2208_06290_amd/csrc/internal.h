@@ -225,3 +225,48 @@ hipError_t launch_pblocks(hipStream_t s, int nparents, int r, const T* Kinv, int
 hipError_t launch_node_mix(hipStream_t s, int64_t n, int L, int R, const int64_t* d_leaf_off, const int32_t* d_rpre,
                            const int64_t* d_pdoff, const double* Pd, int trans, const double* in, double* out);
 }  // namespace hodlr
+
+namespace hodlr {
+// Construction by cross approximation (construct.hip).
+struct ConstructKernel {
+  int kind;
+  int dim;
+  const double* pts;
+  int64_t ldp;
+  const double* nrm;
+  const double* w;
+  const double* kap;
+  double ell;
+  double shift;
+};
+// One sibling block A(I_a, I_b): rows r0 .. r0 + m, columns c0 .. c0 + n, its
+// generators in columns col .. col + rank of U_big / V_big, its tiles
+// tile0 .. tile0 + ntile (each covers aca_tile_elems() rows and columns).
+struct AcaBlock {
+  int64_t r0, c0;
+  int32_t m, n, col, rank, tile0, ntile;
+};
+struct AcaTile {
+  int32_t blk, t, gtile;
+};
+// per-tile partial argmax of the residual rows (modulus, signed value, column)
+// and columns (score, row); pivot rows [block][kmax]
+struct AcaPartials {
+  double* rp_abs;
+  double* rp_val;
+  int* rp_idx;
+  double* cp_abs;
+  int* cp_idx;
+  int* piv;
+};
+int aca_tile_elems();
+template <typename TS>
+hipError_t launch_construct_leaves(hipStream_t s, const ConstructKernel& k, int nleaf, const int64_t* d_off, int m_max,
+                                   TS* D, int64_t ldd);
+// step `step` of every block (rank > step): the residual-row launch and the residual-column launch
+hipError_t launch_aca_step(hipStream_t s, const ConstructKernel& k, int ntiles, const AcaBlock* blocks,
+                           const AcaTile* tiles, int step, int kmax, double* U, int64_t ldu, double* V, int64_t ldv,
+                           AcaPartials p);
+template <typename TS>
+hipError_t launch_store_cols(hipStream_t s, int64_t n, int ncols, const double* src, int64_t lds, TS* dst, int64_t ldd);
+}  // namespace hodlr

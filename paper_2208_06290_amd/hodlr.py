@@ -54,10 +54,18 @@ class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("relres", ctypes.c_double)]
 
 
+class _Kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("dim", ctypes.c_int32), ("points", ctypes.c_void_p), ("ldp", ctypes.c_int64),
+                ("normals", ctypes.c_void_p), ("weights", ctypes.c_void_p), ("curvature", ctypes.c_void_p),
+                ("ell", ctypes.c_double), ("shift", ctypes.c_double)]
+
+
+KERNELS = {"gauss": 0, "matern32": 1, "laplace_dl": 2}
+
 EXPORTS = ["hodlr_factor", "hodlr_refactor", "hodlr_solve", "hodlr_solve_adjoint", "hodlr_solve_noalloc",
            "hodlr_solve_noalloc_bytes", "hodlr_matvec", "hodlr_grad", "hodlr_logdet", "hodlr_logdet_grad",
            "hodlr_factors_y", "hodlr_factor_bytes", "hodlr_destroy", "hodlr_status_string", "hodlr_timing_enable",
-           "hodlr_kernel_times"]
+           "hodlr_kernel_times", "hodlr_construct"]
 
 _lib = None
 
@@ -95,8 +103,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hodlr_kernel_times.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64), i32]
     lib.hodlr_kernel_times.restype = i32
+    lib.hodlr_construct.argtypes = [ctypes.POINTER(_Kernel), i64, i32, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(i32), ctypes.c_int, vp, i64, vp, i64, vp, i64, vp]
     for name in ("hodlr_factor", "hodlr_refactor", "hodlr_solve", "hodlr_solve_adjoint", "hodlr_solve_noalloc",
-                 "hodlr_matvec", "hodlr_grad", "hodlr_logdet", "hodlr_logdet_grad", "hodlr_factors_y"):
+                 "hodlr_matvec", "hodlr_grad", "hodlr_logdet", "hodlr_logdet_grad", "hodlr_factors_y",
+                 "hodlr_construct"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -328,6 +339,59 @@ def factor(A: HODLRMatrix, precision: str = "fp64", raise_singular: bool = True,
         raise HodlrError(st, "hodlr_factor") if st != ERR_SINGULAR else _singular(info)
     inf = dict(level=info.level, column=info.column, node=info.node) if st == ERR_SINGULAR else None
     return Factors(A, h, precision, inf, inplace)
+
+
+def construct(kind: str, points: torch.Tensor, ranks: Sequence[int], leaf_offsets: Optional[Sequence[int]] = None,
+              ell: float = 1.0, shift: float = 0.0, normals: Optional[torch.Tensor] = None,
+              weights: Optional[torch.Tensor] = None, curvature: Optional[torch.Tensor] = None,
+              dtype: torch.dtype = torch.float64) -> HODLRMatrix:
+    """HODLR approximation of a kernel matrix built on the GPU (hodlr_construct):
+    exact leaf blocks and r_l steps of cross approximation with partial
+    pivoting per sibling block.  points: (N, dim) float64 on the device
+    ('gauss', 'matern32': dim 1..3; 'laplace_dl': dim 2 with (N, 2) unit
+    normals, (N,) weights and curvature).  Returns D, U, V in ``dtype``."""
+    if kind not in KERNELS:
+        raise ValueError(f"kind must be one of {sorted(KERNELS)}")
+    lib = load_library()
+    n, dim = int(points.shape[0]), int(points.shape[1])
+    ranks = [int(r) for r in ranks]
+    L = len(ranks)
+    if leaf_offsets is not None:
+        off = np.ascontiguousarray(leaf_offsets, dtype=np.int64)
+        m_max = int(np.max(np.diff(off)))
+    else:
+        if n % (1 << L):
+            raise ValueError("a uniform tree needs 2**L to divide N")
+        off, m_max = None, n >> L
+    dev = points.device
+    P = points.to(torch.float64).t().contiguous()            # N x dim column-major
+    keep = [P]
+    k = _Kernel()
+    k.kind, k.dim, k.points, k.ldp = KERNELS[kind], dim, P.data_ptr(), n
+    k.ell, k.shift = float(ell), float(shift)
+    if kind == "laplace_dl":
+        if normals is None or weights is None or curvature is None:
+            raise ValueError("laplace_dl needs normals, weights and curvature")
+        Nm = normals.to(torch.float64).t().contiguous()
+        Wt = weights.to(torch.float64).contiguous()
+        Kp = curvature.to(torch.float64).contiguous()
+        for t, nm in ((Nm, "normals"), (Wt, "weights"), (Kp, "curvature")):
+            _check_dev(t, nm)
+        keep += [Nm, Wt, Kp]
+        k.normals, k.weights, k.curvature = Nm.data_ptr(), Wt.data_ptr(), Kp.data_ptr()
+    _check_dev(P, "points")
+    R = sum(ranks)
+    D = torch.empty(m_max, n, dtype=dtype, device=dev)
+    U = torch.empty(max(R, 1), n, dtype=dtype, device=dev)[:R]
+    V = torch.empty(max(R, 1), n, dtype=dtype, device=dev)[:R]
+    rc = (ctypes.c_int32 * max(1, L))(*ranks)
+    oc = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if off is not None else ctypes.POINTER(ctypes.c_int64)()
+    st = lib.hodlr_construct(ctypes.byref(k), n, L, oc, rc, F64 if dtype == torch.float64 else F32,
+                             D.data_ptr(), n, U.data_ptr(), n, V.data_ptr(), n, _stream(dev))
+    del keep
+    if st != 0:
+        raise HodlrError(st, "hodlr_construct")
+    return HODLRMatrix(D, U, V, ranks, off)
 
 
 def _singular(info: _Info) -> HodlrError:
