@@ -196,6 +196,7 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override N (same leaf and rank)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 and BF16 refinement paths")
+    ap.add_argument("--no-construct", action="store_true", help="skip timing the GPU construction of the matrix")
     ap.add_argument("--synthetic", action="store_true",
                     help="random generators of the same N, leaf and rank instead of the BIE matrix (same shapes, "
                          "so the same kernels and traffic; used for counter runs)")
@@ -316,6 +317,11 @@ def main():
         roof = dict(roof)
         roof["traffic"] = measured_traffic(roof["kernel"], inp) if headkey == "fp64" else None
 
+    cons = None
+    if cfg in (1, 2, 3) and not args.no_construct:
+        cons = construct_bench(hodlr, W, cfg, N, inp, args.steps, dev, cpu=not args.no_cpu)
+        _say(f"construct: {cons}")
+
     cpu = None
     if not args.no_cpu and cfg == 2:
         _say("cpu baseline: loading the oracle")
@@ -334,7 +340,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": dtype,
-        "data": WORKLOADS[cfg][1],
+        "data": WORKLOADS[cfg][1] if not (args.synthetic and cfg == 2) else
+        "synthetic (seeded random HODLR generators with the BIE workload's N, leaf and rank)",
         "config": {"workload": WORKLOADS[cfg][0], "N": N, "leaf": int(inp.m_max), "levels": inp.levels,
                    "rank": int(inp.ranks[0]) if inp.ranks else 0, "nrhs": nrhs,
                    "storage": "f64" if ssize == 8 else "f32",
@@ -342,10 +349,90 @@ def main():
                    "matrix_bytes": int(inp.D.numel() + inp.U.numel() + inp.V.numel()) * ssize,
                    "device_total_bytes": int(mem[1])},
         **paths,
+        "construct": cons,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
+
+
+def construct_model(N, ranks, m_max, dim, dl, sb):
+    """Algorithmic HBM bytes of the construction: the leaf blocks written once;
+    per level of rank r and step k, the residual rows read k earlier V entries
+    and write one per column, the normalization reads and writes v_k once, the
+    residual columns read k earlier U entries and write one per row, and every
+    entry evaluated reads its point's coordinates (plus normal and weight for
+    the double layer)."""
+    pt = 8 * dim + (24 if dl else 0)
+    leaves = N * m_max * sb + N * pt
+    steps = 0.0
+    for r in ranks:
+        for k in range(r):
+            steps += N * (8 * k + 8) + N * 16 + N * (8 * k + 8) + 2 * N * pt
+    return leaves, steps
+
+
+def construct_bench(hodlr, W, cfg, N, inp, steps, dev, cpu=True):
+    """Time hodlr_construct on the workload's kernel matrix (same points, tree
+    and ranks as the factorized matrix); roofline of the cross-approximation
+    steps against HBM; the construction oracle on a bounded sample."""
+    import numpy as np
+    import torch
+
+    c = W.CONFIGS[cfg]
+    L, ranks = inp.levels, list(inp.ranks)
+    dtype = torch.float64 if c["storage"] == "f64" else torch.float32
+    if cfg == 2:
+        g = W.star_curve(N, device=dev)
+        kind, pts, dim = "laplace_dl", g["points"], 2
+        kw = dict(shift=0.5, normals=g["normals"], weights=g["weights"], curvature=g["curvature"])
+    else:
+        dim = 2 if cfg == 1 else 3
+        kind = "gauss" if cfg == 1 else "matern32"
+        pts = torch.as_tensor(W.kernel_points(N, dim, c["leaf"], 0), device=dev)
+        kw = dict(ell=0.05 if cfg == 1 else 0.1, shift=1e-2 if cfg == 1 else 1e-3)
+    A = hodlr.construct(kind, pts, ranks, dtype=dtype, **kw)  # warm-up
+    del A
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        A = hodlr.construct(kind, pts, ranks, dtype=dtype, **kw)
+        del A
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    hodlr.timing(True)
+    A = hodlr.construct(kind, pts, ranks, dtype=dtype, **kw)
+    kt = hodlr.kernel_times()
+    hodlr.timing(False)
+    del A
+    leaves_b, steps_b = construct_model(N, ranks, int(inp.m_max), dim, kind == "laplace_dl", 8 if dtype == torch.float64 else 4)
+    aca_ms = kt.get("aca_step", (float("nan"), 0))[0]
+    nsteps = kt.get("aca_step", (0, 0))[1]
+    achieved = steps_b / (aca_ms * 1e-3)
+    out = {"kernel_matrix": kind, "ms": ms, "method": f"exact leaves + {ranks[0] if ranks else 0}-step cross "
+           "approximation with partial pivoting per sibling block, FP64",
+           "kernels": {k: {"total_ms": v[0], "launches": v[1]} for k, v in kt.items()},
+           "roofline": {"kernel": "aca_step", "bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9,
+                        "unit": "GB/s", "frac": achieved / PEAK["hbm"], "bytes_per_step": steps_b / max(nsteps, 1),
+                        "traffic": None}}
+    if cpu:
+        import oracle as O
+
+        n2 = min(N, 8192)
+        L2 = int(round(math.log2(n2 // int(inp.m_max))))
+        off2 = np.asarray(inp.leaf_offsets[: (1 << L2) + 1], dtype=np.int64)
+        ph = pts[:n2].double().cpu().numpy()
+        if kind == "laplace_dl":
+            spec = O.KernelSpec(kind, ph, shift=0.5, normals=kw["normals"][:n2].cpu().numpy(),
+                                weights=kw["weights"][:n2].cpu().numpy(), curvature=kw["curvature"][:n2].cpu().numpy())
+        else:
+            spec = O.KernelSpec(kind, ph, ell=kw["ell"], shift=kw["shift"])
+        t1 = time.perf_counter()
+        O.construct_hodlr(spec, off2, ranks[L - L2:])
+        t2 = time.perf_counter()
+        out["cpu_oracle"] = {"seconds": t2 - t1, "kind": "oracle",
+                             "sample": f"leftmost subtree, N={n2}, {L2} levels, same leaf and rank"}
+    return out
 
 
 def measured_traffic(kernel, inp):

@@ -126,19 +126,41 @@ __global__ __launch_bounds__(kCsThreads) void aca_row_kernel(ConstructKernel kd,
   double best = -1.0, bval = 0.0;
   int bj = INT_MAX;
   const int64_t p = b.r0 + i;
+  // the thread's kCsEpt columns advance together through l (independent
+  // loads in flight); each column's terms are still subtracted in order of l
+  double v[kCsEpt];
+  const double* Vb = V + b.c0 + (int64_t)b.col * ldv;
+  const int j0 = tl.t * kCsTile + tid;
+  if (j0 + (kCsEpt - 1) * kCsThreads < b.n) {  // full tile (uniform)
+#pragma unroll
+    for (int e = 0; e < kCsEpt; ++e) v[e] = kernel_offdiag(kd, p, b.c0 + j0 + e * kCsThreads);
+    for (int l = 0; l < k; ++l) {
+      const double c = uk[l];
+      const double* Vl = Vb + (int64_t)l * ldv + j0;
+#pragma unroll
+      for (int e = 0; e < kCsEpt; ++e) v[e] -= c * Vl[e * kCsThreads];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < kCsEpt; ++e) {
+      const int j = j0 + e * kCsThreads;
+      v[e] = 0.0;
+      if (j < b.n) {
+        v[e] = kernel_offdiag(kd, p, b.c0 + j);
+        for (int l = 0; l < k; ++l) v[e] -= uk[l] * Vb[j + (int64_t)l * ldv];
+      }
+    }
+  }
 #pragma unroll
   for (int e = 0; e < kCsEpt; ++e) {
-    const int j = tl.t * kCsTile + e * kCsThreads + tid;
+    const int j = j0 + e * kCsThreads;
     if (j < b.n) {
-      double v = kernel_offdiag(kd, p, b.c0 + j);
-      const double* Vj = V + (b.c0 + j) + (int64_t)b.col * ldv;
-      for (int l = 0; l < k; ++l) v -= uk[l] * Vj[(int64_t)l * ldv];
-      V[(b.c0 + j) + (int64_t)(b.col + k) * ldv] = v;
-      const double av = fabs(v);
+      V[(b.c0 + j) + (int64_t)(b.col + k) * ldv] = v[e];
+      const double av = fabs(v[e]);
       if (av > best) {  // j increases along e: the first of equal moduli stays
         best = av;
         bj = j;
-        bval = v;
+        bval = v[e];
       }
     }
   }
@@ -207,18 +229,38 @@ __global__ __launch_bounds__(kCsThreads) void aca_col_kernel(ConstructKernel kd,
   __syncthreads();
   double best = -2.0;
   int bi = INT_MAX;
+  double u[kCsEpt];
+  const double* Ub = U + b.r0 + (int64_t)b.col * ldu;
+  const int i0 = row0 + tid;
+  if (exhausted) {
+#pragma unroll
+    for (int e = 0; e < kCsEpt; ++e) u[e] = 0.0;
+  } else if (i0 + (kCsEpt - 1) * kCsThreads < b.m) {  // full tile (uniform)
+#pragma unroll
+    for (int e = 0; e < kCsEpt; ++e) u[e] = kernel_offdiag(kd, b.r0 + i0 + e * kCsThreads, b.c0 + j);
+    for (int l = 0; l < k; ++l) {
+      const double c = vk[l];
+      const double* Ul = Ub + (int64_t)l * ldu + i0;
+#pragma unroll
+      for (int e = 0; e < kCsEpt; ++e) u[e] -= c * Ul[e * kCsThreads];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < kCsEpt; ++e) {
+      const int ii = i0 + e * kCsThreads;
+      u[e] = 0.0;
+      if (ii < b.m) {
+        u[e] = kernel_offdiag(kd, b.r0 + ii, b.c0 + j);
+        for (int l = 0; l < k; ++l) u[e] -= vk[l] * Ub[ii + (int64_t)l * ldu];
+      }
+    }
+  }
 #pragma unroll
   for (int e = 0; e < kCsEpt; ++e) {
     const int ii = row0 + e * kCsThreads + tid;
     if (ii < b.m) {
-      double u = 0.0;
-      if (!exhausted) {
-        u = kernel_offdiag(kd, b.r0 + ii, b.c0 + j);
-        const double* Ui = U + (b.r0 + ii) + (int64_t)b.col * ldu;
-        for (int l = 0; l < k; ++l) u -= vk[l] * Ui[(int64_t)l * ldu];
-      }
-      U[(b.r0 + ii) + (int64_t)(b.col + k) * ldu] = u;
-      const double sc = used[ii - row0] ? -1.0 : fabs(u);
+      U[(b.r0 + ii) + (int64_t)(b.col + k) * ldu] = u[e];
+      const double sc = used[ii - row0] ? -1.0 : fabs(u[e]);
       if (sc > best) {
         best = sc;
         bi = ii;
