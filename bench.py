@@ -16,7 +16,8 @@ plus one solve of the right-hand side.  Reported:
              the MI355X peak
   cpu_baseline  the CPU oracle on a bounded sample of the same workload
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu] [--no-mixed]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu] [--no-mixed] [--no-construct]
+       python bench.py --construct-only [--config 1|2|3]   (GPU construction of the kernel matrix only)
        python bench.py --copy-probe     (plain device copy, for counter calibration)
 """
 import argparse
@@ -40,6 +41,14 @@ PEAK = dict(hbm=8.0e12, f64=78.6e12, f32=157.3e12, bf16=2.5e15)
 LEVEL_PASS_TRAFFIC = dict(
     source_sha256="b27927773f753f35361de738cd42de469df5a5011658928c1acc1e600e7a87e2",
     n=1 << 20, leaf=256, rank=32, bytes_per_launch=4.26e9)
+
+# HBM traffic of one cross-approximation step (row + column launch) of the
+# construction of the double-layer matrix at N = 2^20, leaf 256, rank 32, from
+# the same two counter runs and copy calibration (summary and commands in
+# profiles/construct_aca_bie_n1m_fp64.md); reported only for that source.
+CONSTRUCT_TRAFFIC = dict(
+    source_sha256="477a0a4d62ad1017a94fabf7db84e260b0261532df6c4fee0bca09078fe1bae9",
+    n=1 << 20, leaf=256, rank=32, kind="laplace_dl", bytes_per_step=4.2422e9)
 
 
 def _say(*a):
@@ -197,6 +206,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 and BF16 refinement paths")
     ap.add_argument("--no-construct", action="store_true", help="skip timing the GPU construction of the matrix")
+    ap.add_argument("--construct-only", action="store_true",
+                    help="only time the GPU construction of the workload's kernel matrix (no factor / solve)")
     ap.add_argument("--synthetic", action="store_true",
                     help="random generators of the same N, leaf and rank instead of the BIE matrix (same shapes, "
                          "so the same kernels and traffic; used for counter runs)")
@@ -225,6 +236,17 @@ def main():
         return
     cfg = args.config
     c = W.CONFIGS[cfg]
+    if args.construct_only:
+        if cfg not in (1, 2, 3):
+            print("bench.py: --construct-only needs a kernel-matrix workload (--config 1, 2 or 3)", file=sys.stderr)
+            sys.exit(2)
+        N = args.n or c["n"]
+        L = int(round(math.log2(N // c["leaf"])))
+        cons = construct_bench(hodlr, W, cfg, N, W.uniform_offsets(N, L), [c["rank"]] * L, args.steps, dev,
+                               cpu=not args.no_cpu)
+        print(json.dumps({"config": {"workload": WORKLOADS[cfg][0], "N": N, "leaf": c["leaf"], "levels": L,
+                                     "rank": c["rank"]}, "construct": cons}), flush=True)
+        return
     t0 = time.time()
     if args.synthetic and cfg == 2:
         inp = W.synthetic(args.n or c["n"], c["leaf"], c["rank"], seed=0, dtype=torch.float64, device=dev)
@@ -319,7 +341,7 @@ def main():
 
     cons = None
     if cfg in (1, 2, 3) and not args.no_construct:
-        cons = construct_bench(hodlr, W, cfg, N, inp, args.steps, dev, cpu=not args.no_cpu)
+        cons = construct_bench(hodlr, W, cfg, N, inp.leaf_offsets, inp.ranks, args.steps, dev, cpu=not args.no_cpu)
         _say(f"construct: {cons}")
 
     cpu = None
@@ -372,7 +394,7 @@ def construct_model(N, ranks, m_max, dim, dl, sb):
     return leaves, steps
 
 
-def construct_bench(hodlr, W, cfg, N, inp, steps, dev, cpu=True):
+def construct_bench(hodlr, W, cfg, N, leaf_offsets, ranks, steps, dev, cpu=True):
     """Time hodlr_construct on the workload's kernel matrix (same points, tree
     and ranks as the factorized matrix); roofline of the cross-approximation
     steps against HBM; the construction oracle on a bounded sample."""
@@ -380,7 +402,8 @@ def construct_bench(hodlr, W, cfg, N, inp, steps, dev, cpu=True):
     import torch
 
     c = W.CONFIGS[cfg]
-    L, ranks = inp.levels, list(inp.ranks)
+    L, ranks = len(ranks), list(ranks)
+    m_max = int(np.max(np.diff(leaf_offsets)))
     dtype = torch.float64 if c["storage"] == "f64" else torch.float32
     if cfg == 2:
         g = W.star_curve(N, device=dev)
@@ -405,7 +428,7 @@ def construct_bench(hodlr, W, cfg, N, inp, steps, dev, cpu=True):
     kt = hodlr.kernel_times()
     hodlr.timing(False)
     del A
-    leaves_b, steps_b = construct_model(N, ranks, int(inp.m_max), dim, kind == "laplace_dl", 8 if dtype == torch.float64 else 4)
+    leaves_b, steps_b = construct_model(N, ranks, m_max, dim, kind == "laplace_dl", 8 if dtype == torch.float64 else 4)
     aca_ms = kt.get("aca_step", (float("nan"), 0))[0]
     nsteps = kt.get("aca_step", (0, 0))[1]
     achieved = steps_b / (aca_ms * 1e-3)
@@ -414,13 +437,13 @@ def construct_bench(hodlr, W, cfg, N, inp, steps, dev, cpu=True):
            "kernels": {k: {"total_ms": v[0], "launches": v[1]} for k, v in kt.items()},
            "roofline": {"kernel": "aca_step", "bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9,
                         "unit": "GB/s", "frac": achieved / PEAK["hbm"], "bytes_per_step": steps_b / max(nsteps, 1),
-                        "traffic": None}}
+                        "traffic": construct_traffic(kind, N, m_max, ranks)}}
     if cpu:
         import oracle as O
 
         n2 = min(N, 8192)
-        L2 = int(round(math.log2(n2 // int(inp.m_max))))
-        off2 = np.asarray(inp.leaf_offsets[: (1 << L2) + 1], dtype=np.int64)
+        L2 = int(round(math.log2(n2 // m_max)))
+        off2 = np.asarray(leaf_offsets[: (1 << L2) + 1], dtype=np.int64)
         ph = pts[:n2].double().cpu().numpy()
         if kind == "laplace_dl":
             spec = O.KernelSpec(kind, ph, shift=0.5, normals=kw["normals"][:n2].cpu().numpy(),
@@ -433,6 +456,20 @@ def construct_bench(hodlr, W, cfg, N, inp, steps, dev, cpu=True):
         out["cpu_oracle"] = {"seconds": t2 - t1, "kind": "oracle",
                              "sample": f"leftmost subtree, N={n2}, {L2} levels, same leaf and rank"}
     return out
+
+
+def construct_traffic(kind, N, leaf, ranks):
+    """Counter-measured HBM bytes per cross-approximation step, or None when no
+    measurement matches this workload and the current kernel source."""
+    import hashlib
+
+    t = CONSTRUCT_TRAFFIC
+    if kind != t["kind"] or N != t["n"] or leaf != t["leaf"] or any(int(r) != t["rank"] for r in ranks):
+        return None
+    with open(os.path.join(ROOT, "paper_2208_06290_amd", "csrc", "construct.hip"), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
+            return None
+    return t["bytes_per_step"]
 
 
 def measured_traffic(kernel, inp):
