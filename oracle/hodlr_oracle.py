@@ -9,8 +9,9 @@ hierarchically off-diagonal low-rank approximations"):
 * cluster tree / tessellation: Definition "Cluster tree" and the HODLR
   tessellation of Section II-A (leaves give diagonal blocks, sibling pairs
   give off-diagonal blocks);
-* generators: A(I_a, I_b) = U_a V_b^* for siblings a, b (eq. "e:rank"); real
-  field, so V^* = V^T;
+* generators: A(I_a, I_b) = U_a V_b^* for siblings a, b (eq. "e:rank"), V^*
+  the conjugate transpose (V^T for real matrices; complex matrices, the
+  field F = C of the paper, take the same recursion with V^*);
 * recursion (Section III-A): solve A_a [z_a | Y_a] = [b_a | U_a] on each
   child (eq. "e:recursion"), then the coupling system with
   K = [[V_a^T Y_a, I], [I, V_b^T Y_b]] (eqs. "e:node", "e:k"), then
@@ -72,6 +73,11 @@ def node_range(H: Hodlr, level: int, i: int):
     return int(H.offsets[i * per]), int(H.offsets[(i + 1) * per])
 
 
+def _adj(M: np.ndarray) -> np.ndarray:
+    """M^* (the transpose for real M)."""
+    return M.conj().T
+
+
 def _gen(H: Hodlr, which: str, level: int, i: int) -> np.ndarray:
     s, e = node_range(H, level, i)
     c0, c1 = H.colrange(level)
@@ -85,7 +91,7 @@ def _leaf(H: Hodlr, i: int) -> np.ndarray:
 
 
 def assemble_dense(H: Hodlr) -> np.ndarray:
-    """The plain definition: leaves on the diagonal, U_a V_b^T on sibling blocks."""
+    """The plain definition: leaves on the diagonal, U_a V_b^* on sibling blocks."""
     N = H.N
     A = np.zeros((N, N), dtype=H.D.dtype)
     for i in range(1 << H.L):
@@ -96,8 +102,8 @@ def assemble_dense(H: Hodlr) -> np.ndarray:
             a, b = 2 * p, 2 * p + 1
             sa, ea = node_range(H, level, a)
             sb, eb = node_range(H, level, b)
-            A[sa:ea, sb:eb] = _gen(H, "U", level, a) @ _gen(H, "V", level, b).T
-            A[sb:eb, sa:ea] = _gen(H, "U", level, b) @ _gen(H, "V", level, a).T
+            A[sa:ea, sb:eb] = _gen(H, "U", level, a) @ _adj(_gen(H, "V", level, b))
+            A[sb:eb, sa:ea] = _gen(H, "U", level, b) @ _adj(_gen(H, "V", level, a))
     return A
 
 
@@ -106,10 +112,10 @@ def assemble_dense(H: Hodlr) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def _coupling_matrix(Va, Ya, Vb, Yb):
-    """K = [[V_a^T Y_a, I], [I, V_b^T Y_b]]  (eq. "e:k")."""
+    """K = [[V_a^* Y_a, I], [I, V_b^* Y_b]]  (eq. "e:k")."""
     r = Ya.shape[1]
     I = np.eye(r, dtype=Ya.dtype)
-    return np.block([[Va.T @ Ya, I], [I, Vb.T @ Yb]])
+    return np.block([[_adj(Va) @ Ya, I], [I, _adj(Vb) @ Yb]])
 
 
 def _combine(Za, Zb, Ya, Yb, W):
@@ -151,7 +157,7 @@ def _solve(F: dict, B: np.ndarray) -> np.ndarray:
     Zb = _solve(F["b"], B[na:])
     if F["Klu"] is None:
         return np.vstack([Za, Zb])
-    rhs = np.vstack([F["Va"].T @ Za, F["Vb"].T @ Zb])       # right side of eq. "e:node"
+    rhs = np.vstack([_adj(F["Va"]) @ Za, _adj(F["Vb"]) @ Zb])   # right side of eq. "e:node"
     W = sla.lu_solve(F["Klu"], rhs)
     return _combine(Za, Zb, F["Ya"], F["Yb"], W)
 
@@ -234,22 +240,24 @@ def slogdet(F: dict):
 # ---------------------------------------------------------------------------
 
 def transpose(H: Hodlr) -> Hodlr:
-    """A^T is HODLR on the same tree: leaf blocks transposed and U <-> V,
-    because A^T(I_a, I_b) = (U_b V_a^T)^T = V_a U_b^T."""
+    """A^* (A^T for real matrices) is HODLR on the same tree: leaf blocks
+    conjugate-transposed and U <-> V, because
+    A^*(I_a, I_b) = (U_b V_a^*)^* = V_a U_b^*."""
     Dt = np.zeros_like(H.D)
     for i in range(1 << H.L):
         s, e = node_range(H, H.L, i)
-        Dt[s:e, :e - s] = H.D[s:e, :e - s].T
+        Dt[s:e, :e - s] = _adj(H.D[s:e, :e - s])
     return Hodlr(H.offsets, list(H.ranks), Dt, H.V.copy(), H.U.copy())
 
 
 def solve_adjoint(H: Hodlr, G: np.ndarray) -> np.ndarray:
-    """lambda = A^{-T} G, by factoring the transposed HODLR matrix independently."""
+    """lambda = A^{-T} G (A^{-*} G for complex A), by factoring the transposed
+    HODLR matrix independently."""
     return solve(factor(transpose(H)), G)
 
 
 def matvec(H: Hodlr, X: np.ndarray, trans: bool = False) -> np.ndarray:
-    """Y = A X (or A^T X) block by block, without assembling A."""
+    """Y = A X (or A^T X; A^* X for complex A) block by block, without assembling A."""
     if trans:
         H = transpose(H)
     vec = X.ndim == 1
@@ -263,8 +271,8 @@ def matvec(H: Hodlr, X: np.ndarray, trans: bool = False) -> np.ndarray:
             a, b = 2 * p, 2 * p + 1
             sa, ea = node_range(H, level, a)
             sb, eb = node_range(H, level, b)
-            Y[sa:ea] += _gen(H, "U", level, a) @ (_gen(H, "V", level, b).T @ X2[sb:eb])
-            Y[sb:eb] += _gen(H, "U", level, b) @ (_gen(H, "V", level, a).T @ X2[sa:ea])
+            Y[sa:ea] += _gen(H, "U", level, a) @ (_adj(_gen(H, "V", level, b)) @ X2[sb:eb])
+            Y[sb:eb] += _gen(H, "U", level, b) @ (_adj(_gen(H, "V", level, a)) @ X2[sa:ea])
     return Y[:, 0] if vec else Y
 
 

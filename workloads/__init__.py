@@ -12,6 +12,7 @@ from .hodlr_inputs import (  # noqa: F401
     synthetic,
     bie_star,
     kernel_matrix,
+    helmholtz_matrix,
     rcb_order,
     kernel_points,
     star_curve,

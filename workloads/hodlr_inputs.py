@@ -84,11 +84,13 @@ class HodlrInputs:
         )
 
     def numpy64(self):
-        """(offsets, ranks, D (N x m_max), U (N x R), V (N x R)) as float64 numpy."""
+        """(offsets, ranks, D (N x m_max), U (N x R), V (N x R)) as float64
+        numpy (complex128 for complex inputs)."""
+        dt = torch.complex128 if self.D.is_complex() else torch.float64
         return (self.leaf_offsets.copy(), list(self.ranks),
-                self.D.detach().to("cpu", torch.float64).numpy().T,
-                self.U.detach().to("cpu", torch.float64).numpy().T,
-                self.V.detach().to("cpu", torch.float64).numpy().T)
+                self.D.detach().to("cpu", dt).numpy().T,
+                self.U.detach().to("cpu", dt).numpy().T,
+                self.V.detach().to("cpu", dt).numpy().T)
 
 
 def _node_sizes_per_row(offsets: np.ndarray, levels: int, level: int) -> np.ndarray:
@@ -109,7 +111,18 @@ def synthetic(n: int, leaf: int, rank, seed: int = 0, shift: float = 4.0,
 
     ``rank`` is an int (same rank on every level) or a list r_1..r_L.
     ``leaf_offsets`` gives a non-uniform tree (then ``levels`` is implied).
+    dtype=torch.complex128: real parts as for float64, imaginary parts drawn
+    the same way from a second seed (without the shift), generators scaled
+    by 1/sqrt(2) so their columns keep unit expected norm.
     """
+    if dtype == torch.complex128:
+        kw = dict(dtype=torch.float64, device=device, leaf_offsets=leaf_offsets, levels=levels)
+        re = synthetic(n, leaf, rank, seed=seed, shift=shift, **kw)
+        im = synthetic(n, leaf, rank, seed=seed + 7_777_777, shift=0.0, **kw)
+        h = 1.0 / math.sqrt(2.0)
+        return HodlrInputs(n, re.levels, re.leaf_offsets, re.ranks, torch.complex(re.D, im.D),
+                           torch.complex(re.U * h, im.U * h), torch.complex(re.V * h, im.V * h),
+                           name="complex " + re.name, meta=dict(kind="synthetic_complex", seed=seed, shift=shift))
     if leaf_offsets is None:
         if levels is None:
             levels = int(round(math.log2(n // leaf)))
@@ -366,7 +379,7 @@ def _kblock(P: torch.Tensor, ri: torch.Tensor, cj: torch.Tensor, f):
 def _block_apply(P, rows, cols, M, f, budget=1 << 25):
     """(B, n, n) kernel blocks K(rows_b, cols_b) applied to M (B, n, k), chunked."""
     B, n = rows.shape
-    out = torch.empty(B, n, M.shape[2], dtype=torch.float64, device=M.device)
+    out = torch.empty(B, n, M.shape[2], dtype=M.dtype, device=M.device)
     step = max(1, min(n, budget // max(1, B * n)))
     for i0 in range(0, n, step):
         Kc = _kblock(P, rows[:, i0:i0 + step], cols, f)
@@ -421,6 +434,67 @@ def kernel_matrix(n: int, leaf: int, rank: int, kind: str, dim: int, nugget: flo
     return HodlrInputs(n, levels, offsets, [rank] * levels, Dt.to(dtype), U.to(dtype), V.to(dtype),
                        name=f"{kind} kernel N={n} dim={dim} leaf={leaf} r={rank}",
                        meta=dict(kind=kind, dim=dim, nugget=nugget, seed=seed))
+
+
+def helmholtz_matrix(n: int, leaf: int, rank: int, kappa: float = 20.0, seed: int = 0, oversample: int = 10,
+                     power_iters: int = 1, device="cpu") -> HodlrInputs:
+    """Complex symmetric matrix I + h G on N points uniform in [0,1]^3 in RCB
+    order, G_pq = exp(i kappa |x_p - x_q|) / (4 pi |x_p - x_q|) (the 3-D
+    Helmholtz fundamental solution, G_pp = 0), h = 4/N; leaf blocks exact;
+    each sibling pair compressed once by a randomized range finder (complex
+    Gaussian test matrix, oversampling, power iterations, QR, truncated SVD
+    to exactly ``rank``) into A(I_a, I_b) ~= U_a V_b^*; A(I_b, I_a) =
+    A(I_a, I_b)^T then gives U_b = conj(V_b) and V_a = conj(U_a)."""
+    levels = int(round(math.log2(n // leaf)))
+    offsets = uniform_offsets(n, levels)
+    P = torch.as_tensor(kernel_points(n, 3, leaf, seed), dtype=torch.float64, device=device)
+    h = 4.0 / n
+
+    def f(d2):
+        d = torch.sqrt(d2)
+        return h * torch.exp(1j * kappa * d) / (4.0 * math.pi * d)
+
+    nl = 1 << levels
+    idx = torch.arange(n, device=device).view(nl, leaf)
+    Dblk = _kblock(P, idx, idx, f)
+    eye = torch.eye(leaf, dtype=torch.bool, device=device)
+    Dblk = torch.where(eye, torch.ones((), dtype=Dblk.dtype, device=device), Dblk)
+    Dt = Dblk.permute(2, 0, 1).reshape(leaf, n).contiguous()
+    del Dblk
+    R = rank * levels
+    U = torch.empty(R, n, dtype=torch.complex128, device=device)
+    V = torch.empty(R, n, dtype=torch.complex128, device=device)
+    for lvl in range(1, levels + 1):
+        nb = 1 << lvl
+        sz = n // nb
+        nodes = torch.arange(n, device=device).view(nb, sz)
+        a_rows, b_rows = nodes[0::2], nodes[1::2]
+        k = min(rank + oversample, sz)
+        g = _gen(seed, _S_OMEGA, lvl, device)
+        Om = torch.complex(torch.randn(nb // 2, sz, k, generator=g, dtype=torch.float64, device=device),
+                           torch.randn(nb // 2, sz, k, generator=g, dtype=torch.float64, device=device))
+        # A_ab X and A_ab^* X = conj(A_ba conj(X)) (A_ab^T = A_ba)
+        Y = _block_apply(P, a_rows, b_rows, Om, f)
+        for _ in range(power_iters):
+            Q, _r = torch.linalg.qr(Y)
+            Z = _block_apply(P, b_rows, a_rows, Q.conj(), f).conj()
+            Y = _block_apply(P, a_rows, b_rows, Z, f)
+        Q, _r = torch.linalg.qr(Y)                                   # (B, sz, k)
+        Bs = _block_apply(P, b_rows, a_rows, Q.conj(), f).conj()     # B^* = A_ab^* Q, (B, sz, k)
+        W, S, Zh = torch.linalg.svd(Bs, full_matrices=False)         # B^* = W S Zh  ->  B = Zh^* S W^*
+        s = torch.sqrt(S[:, :rank]).to(torch.complex128)
+        Ua = Q @ (Zh.conj().transpose(1, 2)[:, :, :rank] * s[:, None, :])   # A_ab ~= Ua Vb^*
+        Vb = W[:, :, :rank] * s[:, None, :]
+        c0 = (lvl - 1) * rank
+        bu = torch.empty(nb, sz, rank, dtype=torch.complex128, device=device)
+        bv = torch.empty(nb, sz, rank, dtype=torch.complex128, device=device)
+        bu[0::2], bv[1::2] = Ua, Vb
+        bu[1::2], bv[0::2] = Vb.conj(), Ua.conj()
+        U[c0:c0 + rank] = bu.permute(2, 0, 1).reshape(rank, n)
+        V[c0:c0 + rank] = bv.permute(2, 0, 1).reshape(rank, n)
+    return HodlrInputs(n, levels, offsets, [rank] * levels, Dt, U, V,
+                       name=f"Helmholtz 3-D kernel N={n} kappa={kappa} leaf={leaf} r={rank}",
+                       meta=dict(kind="helmholtz", kappa=kappa, seed=seed))
 
 
 # ---------------------------------------------------------------------------
