@@ -45,8 +45,33 @@ extern "C" {
 typedef enum {
   HODLR_F64 = 0,   /* IEEE double                                      */
   HODLR_F32 = 1,   /* IEEE single                                      */
-  HODLR_BF16 = 2   /* bfloat16 MFMA operands, FP32 storage/accumulate  */
+  HODLR_BF16 = 2,  /* bfloat16 MFMA operands, FP32 storage/accumulate  */
+  HODLR_C128 = 3   /* complex double, (re, im) interleaved (storage only) */
 } hodlr_dtype;
+
+/* Complex matrices (the field F = C of the paper; A(I_a, I_b) = U_a V_b^*,
+ * V^* the conjugate transpose).  A hodlr_matrix with dtype HODLR_C128 holds
+ * D, U, V as interleaved complex doubles, leading dimensions counted in
+ * complex elements.  hodlr_factor factors the real embedding of A: entry
+ * p + i q becomes the real 2 x 2 block [[p, -q], [q, p]], and index i the rows
+ * and columns 2i, 2i+1.  The embedding is a real HODLR matrix on the same tree,
+ * with doubled leaf sizes (each leaf <= HODLR_MAX_LEAF / 2) and doubled ranks
+ * (each r_l <= HODLR_MAX_RANK / 2), else HODLR_ERR_UNSUPPORTED.  The
+ * factorization keeps its own embedded copy of D, U, V (the caller's arrays
+ * are read once) and takes compute HODLR_F64, HODLR_F32 or HODLR_BF16 on it;
+ * HODLR_INPLACE is unsupported.  On complex factors:
+ *   - hodlr_solve and hodlr_solve_noalloc (trans = 0) take B as N x nrhs complex
+ *     (interleaved, ldb in complex elements), which is the embedded real vector
+ *     itself: B <- A^{-1} B;
+ *   - hodlr_solve_adjoint and hodlr_solve_noalloc (trans = 1) give
+ *     B <- A^{-*} B (emb(A)^T = emb(A^*));
+ *   - refinement works as for real matrices, on the embedded copy;
+ *   - hodlr_matvec on a complex matrix gives A X, or A^* X when trans = 1;
+ *   - hodlr_factors_y writes the complex Y_big (N x R, ldy in complex elements);
+ *   - hodlr_logdet gives log|det A| with *sign = 1 (0 when singular), because
+ *     det emb(A) = |det A|^2 carries no phase;
+ *   - hodlr_grad and hodlr_logdet_grad return HODLR_ERR_UNSUPPORTED.
+ * The embedding costs twice the bytes and flops of native complex arithmetic. */
 
 typedef enum {
   HODLR_OK = 0,
@@ -84,7 +109,8 @@ typedef enum {
  *   ranks         host, L entries, ranks[l-1] = r_l, 0 <= r_l <= HODLR_MAX_RANK
  *                 and r_l <= size of every level-l node (else HODLR_ERR_ARG).
  *                 May be NULL if L = 0.
- *   dtype         storage type of D, U, V: HODLR_F64 or HODLR_F32
+ *   dtype         storage type of D, U, V: HODLR_F64, HODLR_F32 or HODLR_C128
+ *                 (complex, see "Complex matrices" above)
  *   D, ldd        N x m_max (m_max = largest leaf), ldd >= N
  *   U, ldu        N x R (R = R_L), ldu >= N (ignored if R = 0)
  *   V, ldv        N x R, ldv >= N

@@ -220,6 +220,10 @@ struct hodlr_factors {
   int device = 0;
   std::mutex na_mu;
   hipEvent_t na_done = nullptr;
+  // complex matrices: the factors are those of the real embedding, whose
+  // D, U, V the factorization owns here (n, off, ranks are the embedded ones)
+  int cplx = 0;
+  DevMem emb;
 };
 
 namespace {
@@ -873,7 +877,9 @@ hodlr_status on_stream(hodlr_factors* F, hipStream_t st, int nrhs, Fn fn) {
 hodlr_status solve_common(const hodlr_factors* Fc, int trans, int64_t nrhs, double* B, int64_t ldb,
                           const hodlr_solve_opts* o, void* stream, hodlr_solve_stats* stt) {
   hodlr_factors* F = const_cast<hodlr_factors*>(Fc);
-  if (!F || nrhs < 0 || nrhs > 65535 || (nrhs > 0 && (!B || ldb < F->n))) return HODLR_ERR_ARG;
+  if (!F || nrhs < 0 || nrhs > 65535) return HODLR_ERR_ARG;
+  if (F->cplx) ldb *= 2;  // complex columns: interleaved (re, im), the embedded real vector
+  if (nrhs > 0 && (!B || ldb < F->n)) return HODLR_ERR_ARG;
   if (o && o->refine && F->inplace) return HODLR_ERR_ARG;  // the residual needs the original D and U
   if (nrhs == 0) return HODLR_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -925,6 +931,51 @@ hodlr_status setup(hodlr_factors* F, const hodlr_matrix* A, hodlr_dtype compute,
 hodlr_status grad_impl(hodlr_factors* F, Workspace& Wk, hipStream_t st, int64_t nrhs, const double* X, int64_t ldx,
                        const double* Lam, int64_t ldl, void* dD, void* dU, void* dV);
 
+// Complex matrix A (dtype HODLR_C128) as the real HODLR matrix emb(A): same
+// tree, leaf offsets and ranks doubled, D~ = emb(D) (2N x 2 m_max), U~ =
+// emb(U), V~ = emb(V) (2N x 2R), all with leading dimension 2N.  Validates A
+// and writes the embedded copies into D, U, V (allocated in M when null).
+struct Embedded {
+  hodlr_matrix E{};
+  std::vector<int64_t> off;
+  std::vector<int32_t> ranks;
+};
+hodlr_status embed_complex(const hodlr_matrix* A, hipStream_t st, DevMem& M, Embedded& X, double* D, double* U,
+                           double* V) {
+  if (!A || A->dtype != HODLR_C128) return HODLR_ERR_ARG;
+  hodlr_matrix Ar = *A;
+  Ar.dtype = HODLR_F64;
+  std::vector<int64_t> off;
+  std::vector<int> ranks;
+  int m_max = 0;
+  hodlr_status s = validate(&Ar, off, ranks, m_max);
+  if (s) return s;
+  if (2 * m_max > HODLR_MAX_LEAF) return HODLR_ERR_UNSUPPORTED;
+  int R = 0;
+  for (int r : ranks) {
+    if (2 * r > HODLR_MAX_RANK) return HODLR_ERR_UNSUPPORTED;
+    R += r;
+  }
+  if (A->n > (int64_t(1) << 40)) return HODLR_ERR_UNSUPPORTED;
+  const int64_t n2 = 2 * A->n;
+  if (!D && (s = M.alloc(&D, (size_t)n2 * 2 * m_max))) return s;
+  if (R > 0 && !U && (s = M.alloc(&U, (size_t)n2 * 2 * R))) return s;
+  if (R > 0 && !V && (s = M.alloc(&V, (size_t)n2 * 2 * R))) return s;
+  // the caller's D beyond each leaf's width is embedded too and never read
+  HL("embed", launch_embed_cols(st, A->n, m_max, static_cast<const double*>(A->D), A->ldd, D, n2));
+  if (R > 0) {
+    HL("embed", launch_embed_cols(st, A->n, R, static_cast<const double*>(A->U), A->ldu, U, n2));
+    HL("embed", launch_embed_cols(st, A->n, R, static_cast<const double*>(A->V), A->ldv, V, n2));
+  }
+  X.off.resize(off.size());
+  for (size_t i = 0; i < off.size(); ++i) X.off[i] = 2 * off[i];
+  X.ranks.resize(ranks.size());
+  for (size_t i = 0; i < ranks.size(); ++i) X.ranks[i] = 2 * ranks[i];
+  X.E = hodlr_matrix{n2, A->levels, X.off.data(), X.ranks.empty() ? nullptr : X.ranks.data(), HODLR_F64, D, n2,
+                     R > 0 ? U : nullptr, n2, R > 0 ? V : nullptr, n2};
+  return HODLR_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -936,6 +987,23 @@ hodlr_status hodlr_factor(const hodlr_matrix* A, hodlr_dtype compute, int32_t fl
                           hodlr_factors** out, hodlr_info* info) {
   if (!out) return HODLR_ERR_ARG;
   *out = nullptr;
+  if (A && A->dtype == HODLR_C128) {
+    // factor the real embedding, which the factorization then owns
+    if (flags & HODLR_INPLACE) return HODLR_ERR_UNSUPPORTED;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    DevMem M;
+    Embedded X;
+    hodlr_status s = embed_complex(A, st, M, X, nullptr, nullptr, nullptr);
+    if (s == HODLR_OK) s = hodlr_factor(&X.E, compute, 0, stream, out, info);
+    if (*out) {
+      (*out)->cplx = 1;
+      (*out)->emb = std::move(M);
+    } else {
+      hipStreamSynchronize(st);
+      M.release();
+    }
+    return s;
+  }
   hodlr_factors* F = new hodlr_factors();
   hodlr_status s = setup(F, A, compute, flags);
   if (s == HODLR_OK) s = allocate_factors(F);
@@ -964,14 +1032,25 @@ hodlr_status hodlr_factor(const hodlr_matrix* A, hodlr_dtype compute, int32_t fl
 
 hodlr_status hodlr_refactor(hodlr_factors* F, const hodlr_matrix* A, void* stream, hodlr_info* info) {
   if (!F || !A) return HODLR_ERR_ARG;
+  if ((A->dtype == HODLR_C128) != (F->cplx != 0)) return HODLR_ERR_ARG;
   std::vector<int64_t> off;
   std::vector<int> ranks;
   int m_max = 0;
-  hodlr_status s = validate(A, off, ranks, m_max);
-  if (s) return s;
-  if (A->n != F->n || A->levels != F->L || off != F->off || ranks != F->ranks || A->dtype != F->storage ||
-      A->ldd != F->ldd || A->ldu != F->ldu || A->ldv != F->ldv)
-    return HODLR_ERR_ARG;
+  hodlr_status s;
+  if (F->cplx) {
+    // same tree and ranks; the leading dimensions of the caller's arrays may change
+    hodlr_matrix Ar = *A;
+    Ar.dtype = HODLR_F64;
+    if ((s = validate(&Ar, off, ranks, m_max))) return s;
+    for (auto& o : off) o *= 2;
+    for (auto& r : ranks) r *= 2;
+    if (2 * A->n != F->n || A->levels != F->L || off != F->off || ranks != F->ranks) return HODLR_ERR_ARG;
+  } else {
+    if ((s = validate(A, off, ranks, m_max))) return s;
+    if (A->n != F->n || A->levels != F->L || off != F->off || ranks != F->ranks || A->dtype != F->storage ||
+        A->ldd != F->ldd || A->ldu != F->ldu || A->ldv != F->ldv)
+      return HODLR_ERR_ARG;
+  }
   std::lock_guard<std::mutex> g(F->mu);
   hipStream_t st = static_cast<hipStream_t>(stream);
   // no call on another stream may still read the old factors: hold every
@@ -983,6 +1062,18 @@ hodlr_status hodlr_refactor(hodlr_factors* F, const hodlr_matrix* A, void* strea
   }
   std::lock_guard<std::mutex> gna(F->na_mu);
   if (hipStreamWaitEvent(st, F->na_done, 0) != hipSuccess) return HODLR_ERR_HIP;
+  if (F->cplx) {
+    // new values into the embedded copies the factorization owns
+    DevMem none;
+    Embedded X;
+    if ((s = embed_complex(A, st, none, X, static_cast<double*>(const_cast<void*>(F->D)),
+                           static_cast<double*>(const_cast<void*>(F->U)), static_cast<double*>(const_cast<void*>(F->V)))))
+      return s;
+    s = dispatch_factor(F, st);
+    if (s == HODLR_OK && hipEventRecord(F->ready, st) != hipSuccess) s = HODLR_ERR_HIP;
+    if (s == HODLR_OK) s = verdict(F, st, info);
+    return s;
+  }
   F->D = A->D;
   F->U = A->U;
   F->V = A->V;
@@ -1014,8 +1105,9 @@ size_t hodlr_solve_noalloc_bytes(const hodlr_factors* F, int64_t nrhs) {
 hodlr_status hodlr_solve_noalloc(const hodlr_factors* Fc, int32_t trans, int64_t nrhs, double* B, int64_t ldb,
                                  void* stream) {
   hodlr_factors* F = const_cast<hodlr_factors*>(Fc);
-  if (!F || (trans != 0 && trans != 1) || nrhs < 0 || nrhs > 65535 || (nrhs > 0 && (!B || ldb < F->n)))
-    return HODLR_ERR_ARG;
+  if (!F || (trans != 0 && trans != 1) || nrhs < 0 || nrhs > 65535) return HODLR_ERR_ARG;
+  if (F->cplx) ldb *= 2;
+  if (nrhs > 0 && (!B || ldb < F->n)) return HODLR_ERR_ARG;
   if (nrhs == 0) return HODLR_OK;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return HODLR_ERR_HIP;
@@ -1051,6 +1143,17 @@ hodlr_status hodlr_solve_noalloc(const hodlr_factors* Fc, int32_t trans, int64_t
 hodlr_status hodlr_matvec(const hodlr_matrix* A, int32_t trans, int64_t nrhs, const double* X, int64_t ldx, double* Yo,
                           int64_t ldy, void* stream) {
   if (nrhs < 0 || nrhs > 65535) return HODLR_ERR_ARG;
+  if (A && A->dtype == HODLR_C128) {
+    if (nrhs > 0 && (!X || !Yo || ldx < A->n || ldy < A->n)) return HODLR_ERR_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    DevMem M;
+    Embedded E;
+    hodlr_status s = embed_complex(A, st, M, E, nullptr, nullptr, nullptr);
+    if (s == HODLR_OK) s = hodlr_matvec(&E.E, trans, nrhs, X, 2 * ldx, Yo, 2 * ldy, stream);
+    hipStreamSynchronize(st);
+    M.release();
+    return s;
+  }
   hodlr_factors F;
   std::vector<int64_t> off;
   std::vector<int> ranks;
@@ -1083,6 +1186,7 @@ hodlr_status hodlr_grad(const hodlr_factors* Fc, int64_t nrhs, const double* X, 
   if (!F || nrhs < 1 || nrhs > 65535 || !X || !Lam || ldx < F->n || ldl < F->n || !dD) return HODLR_ERR_ARG;
   if (F->R > 0 && (!dU || !dV)) return HODLR_ERR_ARG;
   if (F->inplace) return HODLR_ERR_ARG;  // the gradients need the original U and V
+  if (F->cplx) return HODLR_ERR_UNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   return on_stream(F, st, (int)nrhs, [&](Workspace& Wk) { return grad_impl(F, Wk, st, nrhs, X, ldx, Lam, ldl, dD, dU, dV); });
 }
@@ -1139,16 +1243,34 @@ hodlr_status grad_impl(hodlr_factors* F, Workspace& Wk, hipStream_t st, int64_t 
 extern "C" {
 
 hodlr_status hodlr_factors_y(const hodlr_factors* F, double* Yo, int64_t ldy, void* stream) {
-  if (!F || (F->R > 0 && (!Yo || ldy < F->n))) return HODLR_ERR_ARG;
+  if (!F || (F->R > 0 && (!Yo || ldy < (F->cplx ? F->n / 2 : F->n)))) return HODLR_ERR_ARG;
   if (F->R == 0) return HODLR_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (F->compute == HODLR_F64)
-    HL("convert", (launch_convert<double, double>(st, F->n, F->R, static_cast<const double*>(F->Y), F->ldy, Yo, ldy,
-                                                  F->gsy)));
-  else
-    HL("convert", (launch_convert<double, float>(st, F->n, F->R, static_cast<const float*>(F->Y), F->ldy, Yo, ldy,
-                                                 F->gsy)));
-  return HODLR_OK;
+  DevMem M;
+  double* Yr = Yo;
+  int64_t ldr = ldy;
+  if (F->cplx) {  // the embedded Y first, then the complex Y from it
+    if (M.alloc(&Yr, (size_t)F->n * F->R)) return HODLR_ERR_ALLOC;
+    ldr = F->n;
+  }
+  auto convert = [&]() -> hodlr_status {
+    if (F->compute == HODLR_F64)
+      HL("convert", (launch_convert<double, double>(st, F->n, F->R, static_cast<const double*>(F->Y), F->ldy, Yr, ldr,
+                                                    F->gsy)));
+    else
+      HL("convert", (launch_convert<double, float>(st, F->n, F->R, static_cast<const float*>(F->Y), F->ldy, Yr, ldr,
+                                                   F->gsy)));
+    // Y~ = emb(Y) (a product of embeddings is the embedding of the product): the
+    // complex Y from the first column of each 2 x 2 block
+    if (F->cplx) HL("embed", launch_deembed_cols(st, F->n / 2, F->R / 2, Yr, F->n, Yo, ldy));
+    return HODLR_OK;
+  };
+  hodlr_status s = convert();
+  if (F->cplx) {
+    hipStreamSynchronize(st);
+    M.release();
+  }
+  return s;
 }
 
 hodlr_status hodlr_logdet(const hodlr_factors* Fc, double* sign, double* logabs, void* stream) {
@@ -1190,6 +1312,12 @@ hodlr_status hodlr_logdet(const hodlr_factors* Fc, double* sign, double* logabs,
   if (s) return s;
   *logabs = res[0];
   *sign = std::isinf(res[0]) && res[0] < 0 ? 0.0 : res[1];
+  if (F->cplx) {
+    // det emb(A) = |det A|^2 >= 0: log|det A| is half of it; the phase of det A
+    // is not available (sign 1, or 0 when singular)
+    *logabs *= 0.5;
+    *sign = *sign == 0.0 ? 0.0 : 1.0;
+  }
   return HODLR_OK;
 }
 
@@ -1314,6 +1442,7 @@ hodlr_status hodlr_logdet_grad(const hodlr_factors* Fc, void* dD, void* dU, void
   hodlr_factors* F = const_cast<hodlr_factors*>(Fc);
   if (!F || !dD || (F->R > 0 && (!dU || !dV))) return HODLR_ERR_ARG;
   if (F->inplace) return HODLR_ERR_ARG;  // needs the original D, U, V
+  if (F->cplx) return HODLR_ERR_UNSUPPORTED;
   if (F->singular) return HODLR_ERR_SINGULAR;  // log|det A| is -inf: no gradient
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (hipStreamWaitEvent(st, F->ready, 0) != hipSuccess) return HODLR_ERR_HIP;
@@ -1335,7 +1464,7 @@ size_t hodlr_factor_bytes(const hodlr_factors* Fc) {
   if (!Fc) return 0;
   hodlr_factors* F = const_cast<hodlr_factors*>(Fc);
   std::lock_guard<std::mutex> g(F->mu);
-  size_t b = F->mem.bytes;
+  size_t b = F->mem.bytes + F->emb.bytes;
   for (auto& kv : F->wsmap) b += kv.second->mem.bytes;
   return b;
 }
@@ -1353,6 +1482,7 @@ void hodlr_destroy(hodlr_factors* F) {
   }
   F->wsmap.clear();
   F->mem.release();
+  F->emb.release();
   hipEventDestroy(F->ready);
   hipEventDestroy(F->na_done);
   delete F;

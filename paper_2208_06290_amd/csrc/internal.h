@@ -270,3 +270,12 @@ hipError_t launch_aca_step(hipStream_t s, const ConstructKernel& k, int ntiles, 
 template <typename TS>
 hipError_t launch_store_cols(hipStream_t s, int64_t n, int ncols, const double* src, int64_t lds, TS* dst, int64_t ldd);
 }  // namespace hodlr
+
+namespace hodlr {
+// Real embedding of complex matrices (embed.hip): E (2n x 2c, ld lde) =
+// emb(M) for complex M (n x c, interleaved, ld ldm in complex elements), and
+// back (M from the first column of each 2 x 2 block).
+hipError_t launch_embed_cols(hipStream_t s, int64_t n, int ncols, const double* M, int64_t ldm, double* E, int64_t lde);
+hipError_t launch_deembed_cols(hipStream_t s, int64_t n, int ncols, const double* E, int64_t lde, double* M,
+                               int64_t ldm);
+}  // namespace hodlr

@@ -20,7 +20,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhodlr.so")
 
-F64, F32, BF16 = 0, 1, 2
+F64, F32, BF16, C128 = 0, 1, 2, 3
 _DT = {"fp64": F64, "fp32": F32, "bf16": BF16}
 INPLACE = 1  # hodlr_factor flag: the factors overwrite D and U
 _STATUS = {0: "ok", -1: "invalid argument", -2: "device allocation failed", -3: "HIP runtime error",
@@ -138,8 +138,8 @@ class HODLRMatrix:
         self.D, self.U, self.V = D, U, V
         R = sum(self.ranks)
         for t, nm in ((D, "D"), (U, "U"), (V, "V")):
-            if t.dtype not in (torch.float64, torch.float32) or t.dtype != D.dtype:
-                raise ValueError("D, U, V must share dtype float64 or float32")
+            if t.dtype not in (torch.float64, torch.float32, torch.complex128) or t.dtype != D.dtype:
+                raise ValueError("D, U, V must share dtype float64, float32 or complex128")
             if t.dim() != 2 or t.shape[1] != self.n or t.stride(1) != 1 or t.stride(0) < self.n:
                 raise ValueError(f"{nm} must be a (k, N) tensor with unit stride along N and row stride >= N")
         if U.shape[0] != R or V.shape[0] != R:
@@ -171,11 +171,15 @@ class HODLRMatrix:
         m.levels = self.levels
         m.leaf_offsets = self._off_c if self._off_c is not None else ctypes.POINTER(ctypes.c_int64)()
         m.ranks = self._ranks_c
-        m.dtype = F64 if self.D.dtype == torch.float64 else F32
+        m.dtype = {torch.float64: F64, torch.float32: F32, torch.complex128: C128}[self.D.dtype]
         m.D, m.ldd = self.D.data_ptr(), self.D.stride(0)
         m.U, m.ldu = self.U.data_ptr(), self.U.stride(0) if self.U.shape[0] > 1 else self.n
         m.V, m.ldv = self.V.data_ptr(), self.V.stride(0) if self.V.shape[0] > 1 else self.n
         return m
+
+    @property
+    def is_complex(self) -> bool:
+        return self.D.dtype == torch.complex128
 
     @property
     def device(self):
@@ -184,7 +188,7 @@ class HODLRMatrix:
     def matvec(self, x: torch.Tensor, trans: bool = False) -> torch.Tensor:
         """FP64 product A x (or A^T x); x is (N,) or (nrhs, N)."""
         lib = load_library()
-        X, vec = _as_rhs(x, self.n)
+        X, vec = _as_rhs(x, self.n, self.is_complex)
         Y = torch.empty_like(X)
         m = self.c_struct()
         st = lib.hodlr_matvec(ctypes.byref(m), int(trans), X.shape[0], X.data_ptr(), self.n, Y.data_ptr(), self.n,
@@ -194,13 +198,15 @@ class HODLRMatrix:
         return Y[0] if vec else Y
 
 
-def _as_rhs(b: torch.Tensor, n: int):
+def _as_rhs(b: torch.Tensor, n: int, cplx: bool = False):
     _check_dev(b, "right-hand side")
     vec = b.dim() == 1
     B = b.reshape(1, -1) if vec else b
     if B.shape[-1] != n:
         raise ValueError(f"right-hand side must have N={n} entries per column")
-    return B.to(torch.float64).contiguous().clone(), vec
+    if B.is_complex() and not cplx:
+        raise ValueError("complex right-hand side for a real matrix")
+    return B.to(torch.complex128 if cplx else torch.float64).contiguous().clone(), vec
 
 
 class Factors:
@@ -236,7 +242,7 @@ class Factors:
 
     def _solve(self, fn, b, refine, tol, max_iter, out_stats, stream=None):
         lib = load_library()
-        X, vec = _as_rhs(b, self.A.n)
+        X, vec = _as_rhs(b, self.A.n, self.A.is_complex)
         o = _Opts(int(refine), int(max_iter), float(tol))
         s = _Stats()
         sp = _stream(self.A.device) if stream is None else ctypes.c_void_p(stream.cuda_stream)
@@ -255,7 +261,7 @@ class Factors:
 
     def solve_adjoint(self, g: torch.Tensor, refine: bool = False, tol: float = 1e-10, max_iter: int = 30,
                       stats: Optional[dict] = None, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
-        """lambda = A^{-T} g (FP64 result)."""
+        """lambda = A^{-T} g (FP64 result; A^{-*} g for a complex A)."""
         return self._solve(load_library().hodlr_solve_adjoint, g, refine, tol, max_iter, stats, stream)
 
     def solve_noalloc_(self, B: torch.Tensor, adjoint: bool = False) -> torch.Tensor:
@@ -264,8 +270,9 @@ class Factors:
         (it is overwritten and returned); no refinement."""
         lib = load_library()
         _check_dev(B, "right-hand side")
-        if B.dtype != torch.float64 or not B.is_contiguous() or B.shape[-1] != self.A.n or B.dim() > 2:
-            raise ValueError("B must be a contiguous float64 (nrhs, N) or (N,) tensor")
+        want = torch.complex128 if self.A.is_complex else torch.float64
+        if B.dtype != want or not B.is_contiguous() or B.shape[-1] != self.A.n or B.dim() > 2:
+            raise ValueError(f"B must be a contiguous {want} (nrhs, N) or (N,) tensor")
         nrhs = 1 if B.dim() == 1 else B.shape[0]
         st = lib.hodlr_solve_noalloc(self._h, int(adjoint), nrhs, B.data_ptr(), self.A.n, _stream(self.A.device))
         if st:
@@ -304,7 +311,8 @@ class Factors:
         """Y_big as an (R, N) float64 tensor (Y_a = A_a^{-1} U_a per level)."""
         lib = load_library()
         R = sum(self.A.ranks)
-        Y = torch.empty(R, self.A.n, dtype=torch.float64, device=self.A.device)
+        dt = torch.complex128 if self.A.is_complex else torch.float64
+        Y = torch.empty(R, self.A.n, dtype=dt, device=self.A.device)
         st = lib.hodlr_factors_y(self._h, Y.data_ptr(), self.A.n, _stream(self.A.device))
         if st:
             raise HodlrError(st, "hodlr_factors_y")
