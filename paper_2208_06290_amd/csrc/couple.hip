@@ -92,82 +92,101 @@ __device__ __forceinline__ float bcast<float>(float v, int srclane) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), srclane));
 }
 
+constexpr int kWlsBatch = 16;
+
 // One wave solves K z = y for NC right-hand-side columns held as x[slot][c]
 // (row = slot * 64 + lane).  Kf: LU factor (col-major, leading dimension ld),
 // kud: reciprocal diagonal.  Rows >= n2 are ignored.
 template <typename T, int NC, int TRANS>
 __device__ __forceinline__ void wave_lu_solve(T (&x)[2][NC], const T* Kf, const T* kud, int n2, int ld, int lane) {
-  if (!TRANS) {
-    // L (unit lower) then U
-    for (int j = 0; j < n2; ++j) {
-      const int sj = j >> 6, lj = j & 63;
-      T xj[NC];
+  // The factor entries a step needs do not depend on x: they are loaded
+  // kWlsBatch steps at a time (one memory latency per batch instead of per
+  // step); rows past n2 load a clamped row and are never used.
+  constexpr int B = kWlsBatch;
+  const int rr[2] = {lane, min(64 + lane, n2 - 1)};
+  auto step_lower = [&](int j, const T (&f)[2]) {  // x(rows > j) -= f x_j (unit diagonal)
+    const int sj = j >> 6, lj = j & 63;
+    T xj[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) xj[c] = bcast(sj ? x[1][c] : x[0][c], lj);
+    for (int c = 0; c < NC; ++c) xj[c] = bcast(sj ? x[1][c] : x[0][c], lj);
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int row = s * 64 + lane;
-        if (row > j && row < n2) {
-          const T f = Kf[row + j * ld];
+    for (int s = 0; s < 2; ++s) {
+      const int row = s * 64 + lane;
+      if (row > j && row < n2) {
 #pragma unroll
-          for (int c = 0; c < NC; ++c) x[s][c] -= f * xj[c];
-        }
+        for (int c = 0; c < NC; ++c) x[s][c] -= f[s] * xj[c];
       }
     }
-    for (int j = n2 - 1; j >= 0; --j) {
-      const int sj = j >> 6, lj = j & 63;
-      const T dinv = kud[j];
-      T xj[NC];
+  };
+  auto step_upper = [&](int j, const T (&f)[2], T dinv, bool below) {  // x_j *= 1/d_j; x(rows beyond j) -= f x_j
+    const int sj = j >> 6, lj = j & 63;
+    T xj[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) xj[c] = bcast(sj ? x[1][c] : x[0][c], lj) * dinv;
+    for (int c = 0; c < NC; ++c) xj[c] = bcast(sj ? x[1][c] : x[0][c], lj) * dinv;
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int row = s * 64 + lane;
-        if (row == j) {
+    for (int s = 0; s < 2; ++s) {
+      const int row = s * 64 + lane;
+      if (row == j) {
 #pragma unroll
-          for (int c = 0; c < NC; ++c) x[s][c] = xj[c];
-        } else if (row < j) {
-          const T f = Kf[row + j * ld];
+        for (int c = 0; c < NC; ++c) x[s][c] = xj[c];
+      } else if (below ? (row > j && row < n2) : (row < j)) {
 #pragma unroll
-          for (int c = 0; c < NC; ++c) x[s][c] -= f * xj[c];
-        }
+        for (int c = 0; c < NC; ++c) x[s][c] -= f[s] * xj[c];
       }
+    }
+  };
+  auto step_lower_back = [&](int j, const T (&f)[2]) {  // x(rows < j) -= f x_j (unit diagonal)
+    const int sj = j >> 6, lj = j & 63;
+    T xj[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xj[c] = bcast(sj ? x[1][c] : x[0][c], lj);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int row = s * 64 + lane;
+      if (row < j) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[s][c] -= f[s] * xj[c];
+      }
+    }
+  };
+  // f[q][s] = entry (row s, step j0 + q): column j of the factor (colmajor) or row j (transposed)
+  auto load = [&](int j0, T (&f)[B][2], T (&dv)[B], bool colmajor, int dir) {
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int j = min(max(j0 + dir * q, 0), n2 - 1);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) f[q][s] = colmajor ? Kf[rr[s] + (int64_t)j * ld] : Kf[j + (int64_t)rr[s] * ld];
+      dv[q] = kud[j];
+    }
+  };
+  T f[B][2], dv[B];
+  if (!TRANS) {
+    // L (unit lower) then U
+    for (int j0 = 0; j0 < n2; j0 += B) {
+      load(j0, f, dv, true, 1);
+#pragma unroll
+      for (int q = 0; q < B; ++q)
+        if (j0 + q < n2) step_lower(j0 + q, f[q]);
+    }
+    for (int j0 = n2 - 1; j0 >= 0; j0 -= B) {
+      load(j0, f, dv, true, -1);
+#pragma unroll
+      for (int q = 0; q < B; ++q)
+        if (j0 - q >= 0) step_upper(j0 - q, f[q], dv[q], false);
     }
   } else {
     // U^T (lower, non-unit) then L^T (unit upper)
-    for (int j = 0; j < n2; ++j) {
-      const int sj = j >> 6, lj = j & 63;
-      const T dinv = kud[j];
-      T xj[NC];
+    for (int j0 = 0; j0 < n2; j0 += B) {
+      load(j0, f, dv, false, 1);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) xj[c] = bcast(sj ? x[1][c] : x[0][c], lj) * dinv;
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int row = s * 64 + lane;
-        if (row == j) {
-#pragma unroll
-          for (int c = 0; c < NC; ++c) x[s][c] = xj[c];
-        } else if (row > j && row < n2) {
-          const T f = Kf[j + row * ld];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) x[s][c] -= f * xj[c];
-        }
-      }
+      for (int q = 0; q < B; ++q)
+        if (j0 + q < n2) step_upper(j0 + q, f[q], dv[q], true);
     }
-    for (int j = n2 - 1; j >= 0; --j) {
-      const int sj = j >> 6, lj = j & 63;
-      T xj[NC];
+    for (int j0 = n2 - 1; j0 >= 0; j0 -= B) {
+      load(j0, f, dv, false, -1);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) xj[c] = bcast(sj ? x[1][c] : x[0][c], lj);
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int row = s * 64 + lane;
-        if (row < j) {
-          const T f = Kf[j + row * ld];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) x[s][c] -= f * xj[c];
-        }
-      }
+      for (int q = 0; q < B; ++q)
+        if (j0 - q >= 0) step_lower_back(j0 - q, f[q]);
     }
   }
 }
@@ -408,69 +427,106 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_kernel(int r, int kp
   }
   if (n2 <= 64) {
     block_lu(K, n2, lane, wid, spiv, sperm, info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16));
-  } else if (wid == 0) {
-    // LU with partial pivoting by one wave (rows over lanes, no block barriers)
+  } else {
+    // LU with partial pivoting, 64 < 2r <= 128: per column, wave 0 takes the
+    // pivot (rows over lanes, two rows a lane), exchanges the rows and scales
+    // the column below the pivot; then the four waves update the trailing
+    // columns, wave w the columns c = w (mod 4) right of j.  Every entry gets
+    // the same operations in the same order as in a sequential elimination.
+    __shared__ T lcol[2 * HODLR_MAX_RANK];
+    __shared__ T prow[2 * HODLR_MAX_RANK];
+    __shared__ int zero_pivot;
     for (int j = 0; j < n2; ++j) {
-      T best = T(-1);
-      int bi = 0x7fffffff;
-#pragma unroll
-      for (int sl = 0; sl < 2; ++sl) {
-        const int row = sl * 64 + lane;
-        if (row >= j && row < n2) {
-          T v = fabs(K[row + j * n2]);
-          if (!(v == v)) v = T(INFINITY);
-          if (v > best || (v == best && row < bi)) {
-            best = v;
-            bi = row;
-          }
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const T ov = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ov > best || (ov == best && oi < bi)) {
-          best = ov;
-          bi = oi;
-        }
-      }
-      const int p = (bi < n2) ? bi : j;
-      if (lane == 0) {
-        spiv[j] = p;
-        if (K[p + j * n2] == T(0))
-          atomicMin(info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16) |
-                              (unsigned long long)j);
-      }
-      if (p != j) {
-#pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
-          const int c = sl * 64 + lane;
-          if (c < n2) {
-            const T t0 = K[j + c * n2];
-            K[j + c * n2] = K[p + c * n2];
-            K[p + c * n2] = t0;
-          }
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const T pivot = K[j + j * n2];
-      if (pivot != T(0)) {
-        const T rinv = T(1) / pivot;
+      if (wid == 0) {
+        T best = T(-1);
+        int bi = 0x7fffffff;
 #pragma unroll
         for (int sl = 0; sl < 2; ++sl) {
           const int row = sl * 64 + lane;
-          if (row > j && row < n2) {
-            const T l = K[row + j * n2] * rinv;
-            K[row + j * n2] = l;
-            for (int c = j + 1; c < n2; ++c) K[row + c * n2] -= l * K[j + c * n2];
+          if (row >= j && row < n2) {
+            T v = fabs(K[row + j * n2]);
+            if (!(v == v)) v = T(INFINITY);
+            if (v > best || (v == best && row < bi)) {
+              best = v;
+              bi = row;
+            }
+          }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const T ov = __shfl_xor(best, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ov > best || (ov == best && oi < bi)) {
+            best = ov;
+            bi = oi;
+          }
+        }
+        const int p = (bi < n2) ? bi : j;
+        if (lane == 0) {
+          spiv[j] = p;
+          if (K[p + j * n2] == T(0))
+            atomicMin(info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16) |
+                                (unsigned long long)j);
+        }
+        if (p != j) {
+#pragma unroll
+          for (int sl = 0; sl < 2; ++sl) {
+            const int c = sl * 64 + lane;
+            if (c < n2) {
+              const T t0 = K[j + c * n2];
+              K[j + c * n2] = K[p + c * n2];
+              K[p + c * n2] = t0;
+            }
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const T pivot = K[j + j * n2];
+        const T rinv = pivot != T(0) ? T(1) / pivot : T(0);
+        if (lane == 0) zero_pivot = pivot == T(0);  // no elimination step then
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+          const int row = sl * 64 + lane;
+          if (row < n2) {
+            // the multipliers below the pivot (zero when the pivot is zero: no update)
+            const T l = row > j ? K[row + j * n2] * rinv : T(0);
+            lcol[row] = l;
+            if (row > j && pivot != T(0)) K[row + j * n2] = l;
+            prow[row] = K[j + row * n2];  // the pivot row (entry c at prow[c])
           }
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      __syncthreads();
+      if (!zero_pivot) {
+        // four of the wave's columns per round, their loads issued together
+        // (rows past n2 read a clamped row and write nothing)
+        const int r0 = lane, r1 = min(64 + lane, n2 - 1);
+        const bool w0 = r0 > j && r0 < n2, w1 = 64 + lane > j && 64 + lane < n2;
+        const T l0 = lcol[r0], l1 = lcol[r1];
+        int c = j + 1 + wid;
+        for (; c + 12 < n2; c += 16) {
+          T a[4], b[4], pc[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            pc[q] = prow[c + 4 * q];
+            a[q] = K[r0 + (c + 4 * q) * n2];
+            b[q] = K[r1 + (c + 4 * q) * n2];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (w0) K[r0 + (c + 4 * q) * n2] = a[q] - l0 * pc[q];
+            if (w1) K[r1 + (c + 4 * q) * n2] = b[q] - l1 * pc[q];
+          }
+        }
+        for (; c < n2; c += 4) {
+          const T pc = prow[c];
+          const T a = K[r0 + c * n2], b = K[r1 + c * n2];
+          if (w0) K[r0 + c * n2] = a - l0 * pc;
+          if (w1) K[r1 + c * n2] = b - l1 * pc;
+        }
+      }
+      __syncthreads();
     }
   }
   __syncthreads();
