@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kLpThreads, 2) void level_pass_kernel(const Tile* _
 // over rows does not depend on their order).
 constexpr int kZtLd = 17;  // padded row length of the per-wave 16 x 16 turn-around buffer
 
-template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE, int RP, bool BF>
+template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE, int RP, bool BF, bool BLK>
 __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level_pass_fast_kernel(
     const Tile* __restrict__ tiles, int zchunks, int c_base, int bchunks, TZ* Z, int64_t ldz, int nz, const SA* __restrict__ A1,
     int64_t lda, const TZ* __restrict__ W, int64_t w_ld, int64_t w_pstride, int node_shift,
@@ -196,6 +196,7 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
   constexpr int kBtLd = 16 * MB + 1;
   constexpr int kWave = 16 * kZtLd + 16 * kBtLd;
   constexpr bool prod = MB > 0;
+  static_assert(MODE != 2 || NCB == 1, "a chunk with a ragged column count is one 16-column block");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TZ* Ws = reinterpret_cast<TZ*>(smem_raw);   // W chunk [ka][kCw]
   TZ* red = reinterpret_cast<TZ*>(smem_raw);  // end of the product: [2][kb][kCw]
@@ -225,10 +226,27 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
     }
   }
 
-  // first row of this wave in each operand (rows inside a tile are contiguous)
-  const auto zr = buf_rsrc(Z + group_row(tl.row0, gs.z) + wr0 + (int64_t)c0 * ldz);
+  // first row of this wave in each operand (rows inside a tile are contiguous).
+  // BLK (product-only passes whose 64-column chunk would need byte offsets
+  // past 2^31, e.g. the FP64 matvec projections at N = 2^22) takes a buffer
+  // resource per 16-column block of Z and of B1, so offsets stay below 16
+  // columns of the leading dimension; otherwise one resource per operand.
+  static_assert(!BLK || NKS == 0, "per-block resources only in product-only passes");
+  constexpr bool kBlk = BLK;
+  constexpr int kZr = kBlk ? NCB : 1;
+  constexpr int kBr = kBlk && MB > 0 ? MB : 1;
+  __amdgpu_buffer_rsrc_t zr[kZr];
+#pragma unroll
+  for (int cb = 0; cb < kZr; ++cb) {
+    // MODE 1: blocks past the valid columns re-read the last valid one
+    const int blk = !kBlk ? 0 : MODE == 1 ? min(cb, (ncz >> 4) - 1) : cb;
+    zr[cb] = buf_rsrc(Z + group_row(tl.row0, gs.z) + wr0 + (int64_t)(c0 + 16 * blk) * ldz);
+  }
   const auto ar = buf_rsrc(NKS > 0 ? A1 + group_row(tl.row0, gs.a) + wr0 : A1);  // A1 / B1 are null when unused
-  const auto br = buf_rsrc(prod ? B1 + group_row(tl.row0, gs.b) + wr0 + (int64_t)kc0 * ldb : B1);
+  __amdgpu_buffer_rsrc_t br[kBr];
+#pragma unroll
+  for (int q = 0; q < kBr; ++q)
+    br[q] = buf_rsrc(prod ? B1 + group_row(tl.row0, gs.b) + wr0 + (int64_t)(kc0 + 16 * q) * ldb : B1);
   const uint32_t zrow = (uint32_t)(RP * li) * (uint32_t)sizeof(TZ);
   const uint32_t zl = zrow + (uint32_t)((int64_t)M::crow_l(lq) * ldz) * (uint32_t)sizeof(TZ);
   const uint32_t al = (uint32_t)(RP * li + (int64_t)lq * lda) * (uint32_t)sizeof(SA);
@@ -247,11 +265,14 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
     if (MODE == 1) return 16 * cb < ncz;
     return 16 * cb + M::crow_u(t) + M::crow_l(lq) < ncz;
   };
+  // the resource of block cb and the column offset inside it
+  auto zrs = [&](int cb) { return zr[kBlk ? cb : 0]; };
   auto zso = [&](int cb, int t) -> uint32_t {
     const int col = MODE == 0   ? 16 * cb + M::crow_u(t)
                     : MODE == 1 ? 16 * min(cb, (ncz >> 4) - 1) + M::crow_u(t)
                                 : min(16 * cb + M::crow_u(t), ncz - 1);
-    return (uint32_t)((int64_t)col * ldz * (int64_t)sizeof(TZ));
+    const int base = !kBlk ? 0 : MODE == 1 ? 16 * min(cb, (ncz >> 4) - 1) : 16 * cb;
+    return (uint32_t)((int64_t)(col - base) * ldz * (int64_t)sizeof(TZ));
   };
   auto zvo = [&](int rb, int cb, int t) -> uint32_t {
     return (MODE < 2 || zok(cb, t) ? zl : zrow) + kRbRows * (uint32_t)rb * (uint32_t)sizeof(TZ);
@@ -262,8 +283,8 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         TZ v0, v1 = TZ(0);
-        if (RP == 2) Buf2<TZ>::load(zr, zvo(rb, cb, t), zso(cb, t), v0, v1);
-        else v0 = Buf<TZ>::load(zr, zvo(rb, cb, t), zso(cb, t));
+        if (RP == 2) Buf2<TZ>::load(zrs(cb), zvo(rb, cb, t), zso(cb, t), v0, v1);
+        else v0 = Buf<TZ>::load(zrs(cb), zvo(rb, cb, t), zso(cb, t));
         d0[cb][t] = zok(cb, t) ? v0 : TZ(0);
         d1[cb][t] = zok(cb, t) ? v1 : TZ(0);
       }
@@ -289,10 +310,14 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
     for (int i = 0; i < 4 * MB; ++i) {
       const bool ok = 4 * i < kbc;  // uniform
       const uint32_t vo = bl + kRbRows * (uint32_t)rb * (uint32_t)sizeof(SB);
-      const uint32_t so = (uint32_t)((int64_t)(ok ? 4 * i : 0) * ldb * (int64_t)sizeof(SB));
+      // column 4 i (inside block i / 4 of its own resource when kBlk), or
+      // column kc0 when past the valid ones
+      const int col = ok ? (kBlk ? 4 * (i % 4) : 4 * i) : 0;
+      const uint32_t so = (uint32_t)((int64_t)col * ldb * (int64_t)sizeof(SB));
+      const auto rs = kBlk && ok ? br[kBlk ? i / 4 : 0] : br[0];
       SB x0, x1 = SB(0);
-      if (RP == 2) Buf2<SB>::load(br, vo, so, x0, x1);
-      else x0 = Buf<SB>::load(br, vo, so);
+      if (RP == 2) Buf2<SB>::load(rs, vo, so, x0, x1);
+      else x0 = Buf<SB>::load(rs, vo, so);
       d0[i] = ok ? (TZ)x0 : TZ(0);
       d1[i] = ok ? (TZ)x1 : TZ(0);
     }
@@ -387,8 +412,8 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
 #pragma unroll
         for (int t = 0; t < 4; ++t)
           if (zok(cb, t)) {
-            if (RP == 2) Buf2<TZ>::store(acc0[cb][t], acc1[cb][t], zr, zvo(rb, cb, t), zso(cb, t));
-            else Buf<TZ>::store(acc0[cb][t], zr, zvo(rb, cb, t), zso(cb, t));
+            if (RP == 2) Buf2<TZ>::store(acc0[cb][t], acc1[cb][t], zrs(cb), zvo(rb, cb, t), zso(cb, t));
+            else Buf<TZ>::store(acc0[cb][t], zrs(cb), zvo(rb, cb, t), zso(cb, t));
           }
     }
     if (prod) {
@@ -435,7 +460,7 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
   }
 }
 
-template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE, int RP, bool BF>
+template <typename TZ, typename SA, typename SB, int MB, int NKS, int NCB, int MODE, int RP, bool BF, bool BLK>
 static hipError_t launch_part(hipStream_t s, int ntiles, int zchunks, int c_base, int nz, int bchunks,
                               const Tile* tiles, TZ* Z, int64_t ldz, const SA* A1, int64_t lda, const TZ* W,
                               int64_t w_ld, int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
@@ -447,7 +472,7 @@ static hipError_t launch_part(hipStream_t s, int ntiles, int zchunks, int c_base
   const size_t smem = smem_main > smem_red ? smem_main : smem_red;
   const int64_t grid = (int64_t)ntiles * zchunks * bchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  auto k = level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, MODE, RP, BF>;
+  auto k = level_pass_fast_kernel<TZ, SA, SB, MB, NKS, NCB, MODE, RP, BF, BLK>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kLpThreads), smem, s, tiles, zchunks, c_base, bchunks, Z, ldz, nz,
@@ -458,35 +483,39 @@ static hipError_t launch_part(hipStream_t s, int ntiles, int zchunks, int c_base
 // Columns of Z in up to three launches: chunks of 64, then the whole 16-column
 // blocks that are left as one narrower chunk, then a last partial block
 // (per-lane column test).  Every launch computes only columns that exist.
-template <typename TZ, typename SA, typename SB, int MB, int NKS, int RP, bool BF>
+template <typename TZ, typename SA, typename SB, int MB, int NKS, int RP, bool BF, bool BLK>
 static hipError_t launch_fast(hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z, int64_t ldz,
                               const SA* A1, int64_t lda, const TZ* W, int64_t w_ld, int64_t w_pstride,
                               int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P, GroupStrides gs) {
   const int n64 = nz / 64, nb = (nz % 64) / 16, tail = nz % 16;
-  hipError_t e = launch_part<TZ, SA, SB, MB, NKS, 4, 0, RP, BF>(s, ntiles, n64, 0, nz, bchunks, tiles, Z, ldz, A1, lda, W,
+  hipError_t e = launch_part<TZ, SA, SB, MB, NKS, 4, 0, RP, BF, BLK>(s, ntiles, n64, 0, nz, bchunks, tiles, Z, ldz, A1, lda, W,
                                                          w_ld, w_pstride, node_shift, B1, ldb, kb, P, gs);
   if (e != hipSuccess) return e;
   const int cb = 64 * n64;
 #define HODLR_LPB(NCBV)                                                                                          \
-  e = launch_part<TZ, SA, SB, MB, NKS, NCBV, 0, RP, BF>(s, ntiles, 1, cb, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,  \
+  e = launch_part<TZ, SA, SB, MB, NKS, NCBV, 0, RP, BF, BLK>(s, ntiles, 1, cb, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,  \
                                                  w_pstride, node_shift, B1, ldb, kb, P, gs)
   if (nb == 1) HODLR_LPB(1);
   else if (nb == 2) HODLR_LPB(2);
   else if (nb == 3) HODLR_LPB(3);
 #undef HODLR_LPB
   if (e != hipSuccess) return e;
-  return launch_part<TZ, SA, SB, MB, NKS, 1, 2, RP, BF>(s, ntiles, tail ? 1 : 0, cb + 16 * nb, nz, bchunks, tiles, Z, ldz, A1,
+  return launch_part<TZ, SA, SB, MB, NKS, 1, 2, RP, BF, BLK>(s, ntiles, tail ? 1 : 0, cb + 16 * nb, nz, bchunks, tiles, Z, ldz, A1,
                                                 lda, W, w_ld, w_pstride, node_shift, B1, ldb, kb, P, gs);
 }
 
-template <typename TZ, typename SA, typename SB, int MB, int RP, bool BF>
+template <typename TZ, typename SA, typename SB, int MB, int RP, bool BF, bool BLK>
 static hipError_t launch_fast_nks(int nks, hipStream_t s, int ntiles, int nz, int bchunks, const Tile* tiles, TZ* Z,
                                   int64_t ldz, const SA* A1, int64_t lda, const TZ* W, int64_t w_ld,
                                   int64_t w_pstride, int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P,
                                   GroupStrides gs) {
 #define HODLR_LPF(NKSV)                                                                                       \
-  return launch_fast<TZ, SA, SB, MB, NKSV, RP, BF>(s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld, w_pstride,      \
+  return launch_fast<TZ, SA, SB, MB, NKSV, RP, BF, BLK>(s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld, w_pstride,      \
                                                  node_shift, B1, ldb, kb, P, gs)
+  if constexpr (BLK) {  // product-only
+    if (nks != 0) return hipErrorInvalidValue;
+    HODLR_LPF(0);
+  } else {
   switch (nks) {
     case 0: HODLR_LPF(0);
     case 4: HODLR_LPF(4);
@@ -494,17 +523,18 @@ static hipError_t launch_fast_nks(int nks, hipStream_t s, int ntiles, int nz, in
     case 12: HODLR_LPF(12);
     default: HODLR_LPF(16);
   }
+  }
 #undef HODLR_LPF
 }
 
-template <typename TZ, typename SA, typename SB, int RP, bool BF>
+template <typename TZ, typename SA, typename SB, int RP, bool BF, bool BLK = false>
 static hipError_t launch_fast_all(hipStream_t s, int ntiles, const Tile* tiles, TZ* Z, int64_t ldz, int nz,
                                   const SA* A1, int64_t lda, int ka, const TZ* W, int64_t w_ld, int64_t w_pstride,
                                   int node_shift, const SB* B1, int64_t ldb, int kb, TZ* P, GroupStrides gs) {
   const int bchunks = kb > 0 ? (kb + 63) / 64 : 1;
   const int nks = ka / 4;
 #define HODLR_LPM(MBV)                                                                                            \
-  return launch_fast_nks<TZ, SA, SB, MBV, RP, BF>(nks, s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,           \
+  return launch_fast_nks<TZ, SA, SB, MBV, RP, BF, BLK>(nks, s, ntiles, nz, bchunks, tiles, Z, ldz, A1, lda, W, w_ld,           \
                                                 w_pstride, node_shift, B1, ldb, kb, P, gs)
   switch (kb > 0 ? std::min(kb, 64) / 16 : 0) {
     case 0: HODLR_LPM(0);
@@ -528,9 +558,15 @@ hipError_t launch_level_pass(hipStream_t s, int ntiles, const Tile* tiles, int t
   if (ka > 64) return hipErrorInvalidValue;
   const int64_t grid = (int64_t)ntiles * zchunks * bchunks;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  // byte offsets inside a tile and chunk must stay below 2^31 for the buffer addressing
+  // byte offsets inside a 64-column chunk must stay below 2^31 for the buffer
+  // addressing; product-only passes may instead address 16-column blocks
   const bool small_ld = 64 * ldz * (int64_t)sizeof(TZ) < (1ll << 31) && 64 * lda * (int64_t)sizeof(SA) < (1ll << 31) &&
                         64 * ldb * (int64_t)sizeof(SB) < (1ll << 31);
+  const bool block_ld = ka == 0 && 16 * ldz * (int64_t)sizeof(TZ) < (1ll << 31) &&
+                        16 * ldb * (int64_t)sizeof(SB) < (1ll << 31);
+  if ((tiles_aligned & 1) && !small_ld && block_ld && kb % 16 == 0)
+    return launch_fast_all<TZ, SA, SB, 1, false, true>(s, ntiles, tiles, Z, ldz, nz, A1, lda, ka, W, w_ld, w_pstride,
+                                                       node_shift, B1, ldb, kb, P, gs);
   if ((tiles_aligned & 1) && small_ld && ka % 16 == 0 && kb % 16 == 0) {
     if constexpr (sizeof(TZ) == 4) {
       // 4-byte elements, tile heights multiples of 32, even leading dimensions and
