@@ -131,10 +131,11 @@ hipError_t launch_matvec_apply(hipStream_t s, int trans, int nleaf, int L, const
   else                                                                                                            \
     hipLaunchKernelGGL((matvec_apply_kernel<S, TR, NC, false>), grid, dim3(kMvThreads), 0, s, d_leaf_off, L, d_rpre, \
                        R, D, ldd, Ua, lda, X, ldx, tree, Y, ldy, nrhs, zchunks)
+  // chunks of 64 columns; up to 16 or 32 columns a narrower instance (one chunk, no padded MFMA columns)
   if (trans) {
-    if (nrhs <= 16) { HODLR_MV(1, 1); } else { HODLR_MV(1, 4); }
+    if (nrhs <= 16) { HODLR_MV(1, 1); } else if (nrhs <= 32) { HODLR_MV(1, 2); } else { HODLR_MV(1, 4); }
   } else {
-    if (nrhs <= 16) { HODLR_MV(0, 1); } else { HODLR_MV(0, 4); }
+    if (nrhs <= 16) { HODLR_MV(0, 1); } else if (nrhs <= 32) { HODLR_MV(0, 2); } else { HODLR_MV(0, 4); }
   }
 #undef HODLR_MV
   return hipGetLastError();

@@ -145,12 +145,13 @@ def test_adjoint_matches_oracle(name):
     assert abs(np.sum(x * G) - np.sum(b * lam)) < 1e-12 * abs(np.sum(x * G)) + 1e-12
 
 
+@pytest.mark.parametrize("nrhs", [5, 20, 70])
 @pytest.mark.parametrize("name", ["cfg0_like", "ragged_L6", "L0_leaf200"])
 @pytest.mark.parametrize("trans", [False, True])
-def test_matvec_matches_oracle(name, trans):
-    _say(f"matvec {name} trans={trans}")
+def test_matvec_matches_oracle(name, trans, nrhs):
+    _say(f"matvec {name} trans={trans} nrhs={nrhs}")
     inp, H, A = _build(name, seed=4)
-    X = _rhs(H.N, 5, 6)
+    X = _rhs(H.N, nrhs, 6)
     Y = _from_dev(A.matvec(_to_dev(X), trans=trans))
     assert _rel(Y, O.matvec(H, X, trans=trans)) < 1e-13
 
