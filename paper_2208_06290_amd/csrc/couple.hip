@@ -671,12 +671,223 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_inv_kernel(int r, in
   }
 }
 
+// Gauss-Jordan elimination as block_gj for 64 < n2 <= 128 (n2 % 16 == 0):
+// eight waves, wave w holding columns 16w .. 16w+15 of K and of the
+// augmented block, lane i holding rows i (slot 0) and 64 + i (slot 1).  The
+// pivot of column j is the largest modulus among the rows not pivoted yet,
+// the lowest current position on ties (the rule of LU with partial
+// pivoting); spiv / spv and the final placement of the rows as block_gj.
+template <typename T>
+__device__ __forceinline__ void block_gj2(T* K, int n2, int lane, int w, int* spiv, T* spv, unsigned long long* info,
+                                          unsigned long long info_base) {
+  __shared__ T s_l[2][128];
+  __shared__ int s_pl[2][3];  // pivot lane, pivot slot, pivot value nonzero
+  T kc[2][16], ac[2][16];
+#pragma unroll
+  for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int row = 64 * sl + lane, col = 16 * w + c;
+      kc[sl][c] = (row < n2 && col < n2) ? K[row + col * n2] : T(0);
+      ac[sl][c] = (row < n2 && row == col) ? T(1) : T(0);
+    }
+  int mypos[2] = {lane, 64 + lane};
+  bool done[2] = {lane >= n2, 64 + lane >= n2};
+  const int nb = n2 >> 4;
+  for (int jb = 0; jb < nb; ++jb) {
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = 16 * jb + jj;
+      const int sb = jj & 1;
+      if (w == jb) {
+        T v[2];
+        int key[2];
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+          T a = fabs(kc[sl][jj]);
+          if (!(a == a)) a = T(INFINITY);
+          v[sl] = done[sl] ? T(-1) : a;
+          key[sl] = done[sl] ? 0x7fffffff : mypos[sl];
+        }
+        const int bs = (v[1] > v[0] || (v[1] == v[0] && key[1] < key[0])) ? 1 : 0;
+        const T vb = bs ? v[1] : v[0];
+        const int kb = bs ? key[1] : key[0];
+        T vmax;
+        int bk;  // position of the pivot row (uniform)
+        wave_argmax(vb, kb, vmax, bk);
+        const unsigned long long sel = __ballot(kb == bk);  // positions of rows not pivoted are distinct
+        const int plane = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(sel));
+        const int pslot = __builtin_amdgcn_readlane(bs, plane);
+        const T pv = bcast(pslot ? kc[1][jj] : kc[0][jj], plane);
+        const bool nz = pv != T(0);
+        const T rp = T(1) / pv;
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+          const int row = 64 * sl + lane;
+          if (row < n2) s_l[sb][row] = nz ? ((lane == plane && sl == pslot) ? rp : kc[sl][jj] * rp) : T(0);
+        }
+        if (lane == 0) {
+          s_pl[sb][0] = plane;
+          s_pl[sb][1] = pslot;
+          s_pl[sb][2] = nz;
+          spiv[j] = bk;
+          spv[j] = pv;
+          if (!nz) atomicMin(info, info_base | (unsigned long long)j);
+        }
+      }
+      __syncthreads();
+      const int plane = __builtin_amdgcn_readfirstlane(s_pl[sb][0]);
+      const int pslot = __builtin_amdgcn_readfirstlane(s_pl[sb][1]);
+      const bool nz = s_pl[sb][2] != 0;
+      T l[2];
+      bool me[2];
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        l[sl] = s_l[sb][min(64 * sl + lane, n2 - 1)];
+        me[sl] = lane == plane && sl == pslot;
+      }
+      const int bk = __builtin_amdgcn_readfirstlane(__shfl(pslot ? mypos[1] : mypos[0], plane, 64));
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        if (!done[sl] && !me[sl] && mypos[sl] == j) mypos[sl] = bk;  // the row displaced by the interchange
+        if (me[sl]) {
+          done[sl] = true;
+          mypos[sl] = j;
+        }
+      }
+      if (nz) {  // uniform; a zero pivot (reported) leaves the rows as they are
+        auto elim = [&](T (&x)[2]) {
+          const T p = bcast(pslot ? x[1] : x[0], plane);
+#pragma unroll
+          for (int sl = 0; sl < 2; ++sl) x[sl] = me[sl] ? x[sl] * l[sl] : x[sl] - l[sl] * p;
+        };
+        auto elim_col = [&](T (&m)[2][16], int c) {
+          T x[2] = {m[0][c], m[1][c]};
+          elim(x);
+          m[0][c] = x[0];
+          m[1][c] = x[1];
+        };
+        if (w == jb) {
+#pragma unroll
+          for (int c = jj + 1; c < 16; ++c) elim_col(kc, c);
+        } else if (w > jb) {
+#pragma unroll
+          for (int c = 0; c < 16; ++c) elim_col(kc, c);
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) elim_col(ac, c);
+      }
+    }
+  }
+  __syncthreads();  // every wave has read K before it is overwritten
+#pragma unroll
+  for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int row = 64 * sl + lane, col = 16 * w + c;
+      if (row < n2 && col < n2) K[mypos[sl] + col * n2] = ac[sl][c];
+    }
+}
+
+// Coupling factor for 64 < 2r <= 128 (2r % 16 == 0): K^{-1} by block_gj2 with
+// eight waves, stored (2r x 2r, col-major), and W = K^{-1} rhs on MFMA
+// (transposed, as couple_factor_inv_kernel): wave w forms rows 16w .. 16w+15.
+constexpr int kCf2Threads = 512;
+template <typename T>
+__global__ __launch_bounds__(kCf2Threads) void couple_factor_inv2_kernel(int r, int Rp, const T* __restrict__ segs,
+                                                                         const int32_t* __restrict__ seg_start,
+                                                                         T* __restrict__ Kinv,
+                                                                         int32_t* __restrict__ Kpiv,
+                                                                         T* __restrict__ Kud, T* __restrict__ W,
+                                                                         unsigned long long* info, int level, int L) {
+  using M = Mfma<T>;
+  using V = typename M::V;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* K = reinterpret_cast<T*>(smem_raw);  // n2 x n2 col-major, then the rhs chunk [c][k] (ld n2 + 1)
+  const int g = blockIdx.x;
+  const int a = 2 * g, b = 2 * g + 1;
+  const int n2 = 2 * r;
+  const int ncin = Rp + r;
+  const int64_t elems = (int64_t)r * ncin;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lq = lane >> 4;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const T* Pa = segs + (int64_t)seg_start[a] * elems;
+  const T* Pb = segs + (int64_t)seg_start[b] * elems;
+  __shared__ int s_piv[128];
+  __shared__ T s_pv[128];
+  for (int e = tid; e < n2 * n2; e += kCf2Threads) {
+    const int i = e % n2, j = e / n2;
+    const bool da = i < r && j < r, db = i >= r && j >= r;
+    const T va = Pa[min(i, r - 1) + (int64_t)(Rp + min(j, r - 1)) * r];
+    const T vb = Pb[max(i - r, 0) + (int64_t)(Rp + max(j - r, 0)) * r];
+    const T id = (i < r ? j - r == i : i - r == j) ? T(1) : T(0);
+    K[i + j * n2] = da ? va : (db ? vb : id);
+  }
+  __syncthreads();
+  block_gj2(K, n2, lane, wid, s_piv, s_pv, info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16));
+  __syncthreads();
+  T* Kg = Kinv + (int64_t)g * n2 * n2;
+  for (int e = tid; e < n2 * n2; e += kCf2Threads) Kg[e] = K[e];
+  if (tid < n2) {
+    Kpiv[(int64_t)g * n2 + tid] = s_piv[tid];
+    Kud[(int64_t)g * n2 + tid] = T(1) / s_pv[tid];
+  }
+  // B operand: K^{-1}(16 wid + li, 4 ks + lq)
+  const bool act = 16 * wid < n2;  // uniform
+  T bk[32];
+#pragma unroll
+  for (int ks = 0; ks < 32; ++ks) bk[ks] = (act && 4 * ks < n2) ? K[(16 * wid + li) + (4 * ks + lq) * n2] : T(0);
+  __syncthreads();  // K's LDS is reused for the right-hand sides
+  T* Rs = K;
+  const int ldr = n2 + 1;
+  T* Wg = W + (int64_t)g * n2 * Rp;
+  for (int c0 = 0; c0 < Rp; c0 += 64) {
+    for (int e = tid; e < 64 * n2; e += kCf2Threads) {
+      const int k = e % n2, c = e / n2;
+      const int col = min(c0 + c, Rp - 1);
+      const T v = k < r ? Pa[k + (int64_t)col * r] : Pb[(k - r) + (int64_t)col * r];
+      Rs[c * ldr + k] = (c0 + c < Rp) ? v : T(0);
+    }
+    __syncthreads();
+    if (act) {
+      V acc[4];
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) acc[mb] = vzero<V>();
+#pragma unroll
+      for (int ks = 0; ks < 32; ++ks) {
+        if (4 * ks < n2) {  // uniform
+#pragma unroll
+          for (int mb = 0; mb < 4; ++mb) acc[mb] = M::mma(Rs[(16 * mb + li) * ldr + 4 * ks + lq], bk[ks], acc[mb]);
+        }
+      }
+      const int i = 16 * wid + li;
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int c = c0 + 16 * mb + M::crow(lq, t);
+          if (c < Rp) Wg[i + (int64_t)c * n2] = acc[mb][t];
+        }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 hipError_t launch_couple_factor(hipStream_t s, int nparents, int r, int kp, int Rp, const T* segs,
                                 const int32_t* d_seg_start, T* Klu, int32_t* Kpiv, int32_t* Kperm, T* Kud, T* Kinv,
                                 T* W, unsigned long long* info, int level, int L) {
   if (nparents == 0 || r == 0) return hipSuccess;
   if (kp > 128) return hipErrorInvalidValue;
+  if (couple_uses_inverse(r) && 2 * r > 64) {
+    const size_t smem_inv = sizeof(T) * std::max<size_t>((size_t)4 * r * r, (size_t)64 * (2 * r + 1));
+    auto ki = couple_factor_inv2_kernel<T>;
+    hipError_t e = hipFuncSetAttribute((const void*)ki, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_inv);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ki, dim3(nparents), dim3(kCf2Threads), smem_inv, s, r, Rp, segs, d_seg_start, Klu, Kpiv, Kud, W,
+                       info, level, L);
+    return hipGetLastError();
+  }
   if (couple_uses_inverse(r)) {
     const size_t smem_inv = sizeof(T) * std::max<size_t>((size_t)4 * r * r, (size_t)64 * (2 * r + 1));
     auto ki = couple_factor_inv_kernel<T>;
@@ -823,14 +1034,15 @@ __global__ __launch_bounds__(64) void couple_solve_reg_kernel(int r, int kp, int
   }
 }
 
-// Solves with an explicit K^{-1} (factors from couple_factor_inv_kernel):
-// one wave per parent, lane i forms row i of w = K^{-1} rhs (TRANS: K^{-T}
-// rhs), the right-hand-side columns broadcast from LDS.
-template <typename T, int TRANS>
+// Solves with an explicit K^{-1} (factors from couple_factor_inv_kernel or
+// couple_factor_inv2_kernel): one wave per parent, lane i forms rows
+// i + 64 s (s < NS) of w = K^{-1} rhs (TRANS: K^{-T} rhs), the
+// right-hand-side columns broadcast from LDS.
+template <typename T, int TRANS, int NS>
 __global__ __launch_bounds__(64) void couple_apply_kernel(int r, int nrhs, const T* __restrict__ segs,
                                                           const int32_t* __restrict__ seg_start,
                                                           const T* __restrict__ Kinv, T* __restrict__ w) {
-  __shared__ T xs[kCsCols * 64];
+  __shared__ T xs[kCsCols * 64 * NS];
   const int g = blockIdx.x;
   const int a = 2 * g, b = 2 * g + 1;
   const int n2 = 2 * r;
@@ -838,32 +1050,48 @@ __global__ __launch_bounds__(64) void couple_apply_kernel(int r, int nrhs, const
   const int64_t elems = (int64_t)r * nrhs;
   const T* Kg = Kinv + (int64_t)g * n2 * n2;
   T* wg = w + (int64_t)g * n2 * nrhs;
-  const bool valid = lane < n2;
-  const int ln = valid ? lane : 0;
-  const int64_t sbase = (int64_t)seg_start[ln < r ? a : b] * elems + (ln % r);
+  bool valid[NS];
+  int ln[NS];
+  int64_t sbase[NS];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int row = 64 * sl + lane;
+    valid[sl] = row < n2;
+    ln[sl] = valid[sl] ? row : 0;
+    sbase[sl] = (int64_t)seg_start[ln[sl] < r ? a : b] * elems + (ln[sl] % r);
+  }
   for (int c0 = 0; c0 < nrhs; c0 += kCsCols) {
 #pragma unroll
-    for (int c = 0; c < kCsCols; ++c) {
-      const T v = segs[sbase + (int64_t)min(c0 + c, nrhs - 1) * r];
-      xs[c * 64 + lane] = (valid && c0 + c < nrhs) ? v : T(0);
-    }
+    for (int sl = 0; sl < NS; ++sl)
+#pragma unroll
+      for (int c = 0; c < kCsCols; ++c) {
+        const T v = segs[sbase[sl] + (int64_t)min(c0 + c, nrhs - 1) * r];
+        xs[c * 64 * NS + 64 * sl + lane] = (valid[sl] && c0 + c < nrhs) ? v : T(0);
+      }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    T acc[kCsCols];
+    T acc[NS][kCsCols];
 #pragma unroll
-    for (int c = 0; c < kCsCols; ++c) acc[c] = T(0);
+    for (int sl = 0; sl < NS; ++sl)
+#pragma unroll
+      for (int c = 0; c < kCsCols; ++c) acc[sl][c] = T(0);
 #pragma unroll 8
     for (int k = 0; k < n2; ++k) {
-      const T kv = TRANS ? Kg[k + (int64_t)ln * n2] : Kg[ln + (int64_t)k * n2];
 #pragma unroll
-      for (int c = 0; c < kCsCols; ++c) acc[c] += kv * xs[c * 64 + k];
-    }
-    if (valid) {
+      for (int sl = 0; sl < NS; ++sl) {
+        const T kv = TRANS ? Kg[k + (int64_t)ln[sl] * n2] : Kg[ln[sl] + (int64_t)k * n2];
 #pragma unroll
-      for (int c = 0; c < kCsCols; ++c)
-        if (c0 + c < nrhs) wg[lane + (int64_t)(c0 + c) * n2] = acc[c];
+        for (int c = 0; c < kCsCols; ++c) acc[sl][c] += kv * xs[c * 64 * NS + k];
+      }
     }
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl)
+      if (valid[sl]) {
+#pragma unroll
+        for (int c = 0; c < kCsCols; ++c)
+          if (c0 + c < nrhs) wg[64 * sl + lane + (int64_t)(c0 + c) * n2] = acc[sl][c];
+      }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -875,12 +1103,17 @@ hipError_t launch_couple_solve(hipStream_t s, int trans, int nparents, int r, in
                                const int32_t* d_seg_start, const T* Klu, const int32_t* Kperm, const T* Kud, T* w) {
   if (nparents == 0 || r == 0 || nrhs == 0) return hipSuccess;
   if (couple_uses_inverse(r)) {
-    if (trans)
-      hipLaunchKernelGGL((couple_apply_kernel<T, 1>), dim3(nparents), dim3(64), 0, s, r, nrhs, segs, d_seg_start,
-                         Klu, w);
-    else
-      hipLaunchKernelGGL((couple_apply_kernel<T, 0>), dim3(nparents), dim3(64), 0, s, r, nrhs, segs, d_seg_start,
-                         Klu, w);
+#define HODLR_CA(TR, NS)                                                                                            \
+  hipLaunchKernelGGL((couple_apply_kernel<T, TR, NS>), dim3(nparents), dim3(64), 0, s, r, nrhs, segs, d_seg_start, \
+                     Klu, w)
+    if (2 * r > 64) {
+      if (trans) HODLR_CA(1, 2);
+      else HODLR_CA(0, 2);
+    } else {
+      if (trans) HODLR_CA(1, 1);
+      else HODLR_CA(0, 1);
+    }
+#undef HODLR_CA
     return hipGetLastError();
   }
   if (2 * r <= 64) {

@@ -119,12 +119,13 @@ template <typename T>
 hipError_t launch_segment_reduce(hipStream_t s, int nsegs, const int2* d_desc, int64_t elems, const T* P, T* out,
                                  int maxy);
 
-// Coupling systems with 2r <= 64 and 2r % 16 == 0 are inverted explicitly
-// (Gauss-Jordan with partial pivoting): the factor stores K^{-1} (2r x 2r,
+// Coupling systems with 2r <= 128 and 2r % 16 == 0 are inverted explicitly
+// (Gauss-Jordan with partial pivoting; four waves up to 2r = 64, eight
+// beyond, two rows a lane): the factor stores K^{-1} (2r x 2r,
 // col-major) in place of the LU, W receives K^{-1} rhs directly and the solves
 // apply K^{-1} or its transpose.  Other ranks keep the LU, its 16 x 16 diagonal
 // inverses and the block solver.
-__host__ __device__ inline bool couple_uses_inverse(int r) { return r > 0 && 2 * r <= 64 && (2 * r) % 16 == 0; }
+__host__ __device__ inline bool couple_uses_inverse(int r) { return r > 0 && 2 * r <= 128 && (2 * r) % 16 == 0; }
 
 // Coupling factor for all parents of one level (children have rank r, W has Rp columns);
 // K factors stored kp x kp (kp = 2r rounded up to 16); W gets the unsolved right-hand
