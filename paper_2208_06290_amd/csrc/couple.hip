@@ -327,33 +327,36 @@ __device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, int* spi
   int mypos = lane;
   bool done = lane >= n2;
   const int nb = n2 >> 4;
+  // pivot search of column j (value kj of the lane's row), by the wave that
+  // owns the column: the multipliers and the pivot go to slot sb
+  auto pivot = [&](int j, T kj, int sb) {
+    T v = done ? T(-1) : fabs(kj);
+    if (!done && !(v == v)) v = T(INFINITY);
+    T vmax;
+    int bk;  // pivot position (uniform)
+    wave_argmax(v, done ? 0x7fffffff : mypos, vmax, bk);
+    const unsigned long long sel = __ballot(!done && mypos == bk);
+    const int plane = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(sel));
+    const T pv = bcast(kj, plane);
+    const bool nz = pv != T(0);
+    const T rp = T(1) / pv;
+    // multipliers of the other rows; the pivot row's own entry is the scale 1 / pivot
+    s_l[sb][lane] = (lane < n2 && nz) ? (lane == plane ? rp : kj * rp) : T(0);
+    if (lane == 0) {
+      s_pl[sb][0] = plane;
+      s_pl[sb][1] = nz;
+      spiv[j] = bk;
+      spv[j] = pv;
+      if (!nz) atomicMin(info, info_base | (unsigned long long)j);
+    }
+  };
   for (int jb = 0; jb < nb; ++jb) {
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
       const int j = 16 * jb + jj;
       const int sb = jj & 1;
-      if (w == jb) {
-        const T kj = kc[jj];
-        T v = done ? T(-1) : fabs(kj);
-        if (!done && !(v == v)) v = T(INFINITY);
-        T vmax;
-        int bk;  // pivot position (uniform)
-        wave_argmax(v, done ? 0x7fffffff : mypos, vmax, bk);
-        const unsigned long long sel = __ballot(!done && mypos == bk);
-        const int plane = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(sel));
-        const T pv = bcast(kj, plane);
-        const bool nz = pv != T(0);
-        const T rp = T(1) / pv;
-        // multipliers of the other rows; the pivot row's own entry is the scale 1 / pivot
-        s_l[sb][lane] = (lane < n2 && nz) ? (lane == plane ? rp : kj * rp) : T(0);
-        if (lane == 0) {
-          s_pl[sb][0] = plane;
-          s_pl[sb][1] = nz;
-          spiv[j] = bk;
-          spv[j] = pv;
-          if (!nz) atomicMin(info, info_base | (unsigned long long)j);
-        }
-      }
+      // the first column of a block; the others were searched ahead (below)
+      if (jj == 0 && w == jb) pivot(j, kc[0], sb);
       __syncthreads();
       const int plane = __builtin_amdgcn_readfirstlane(s_pl[sb][0]);
       const bool nz = s_pl[sb][1] != 0;
@@ -365,19 +368,28 @@ __device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, int* spi
         done = true;
         mypos = j;
       }
-      if (nz) {  // uniform; a zero pivot (reported) leaves the rows as they are
-        auto elim = [&](T& x) {
-          const T p = bcast(x, plane);
-          x = me ? x * l : x - l * p;
-        };
-        // columns left of j are zero in the pivot row: nothing to do there
-        if (w == jb) {
-#pragma unroll
-          for (int c = jj + 1; c < 16; ++c) elim(kc[c]);
-        } else if (w > jb) {
-#pragma unroll
-          for (int c = 0; c < 16; ++c) elim(kc[c]);
+      auto elim = [&](T& x) {
+        const T p = bcast(x, plane);
+        x = me ? x * l : x - l * p;
+      };
+      // columns left of j are zero in the pivot row: nothing to do there.
+      // The owner eliminates column j + 1 first and searches its pivot
+      // before the rest of its work (a zero pivot, reported, leaves the rows
+      // as they are), so that search is off the other waves' critical path.
+      if (w == jb) {
+        if (jj < 15) {
+          if (nz) elim(kc[jj + 1]);
+          pivot(j + 1, kc[jj + 1], sb ^ 1);
         }
+        if (nz) {
+#pragma unroll
+          for (int c = jj + 2; c < 16; ++c) elim(kc[c]);
+        }
+      } else if (w > jb && nz) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) elim(kc[c]);
+      }
+      if (nz) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) elim(ac[c]);
       }
@@ -694,47 +706,52 @@ __device__ __forceinline__ void block_gj2(T* K, int n2, int lane, int w, int* sp
   int mypos[2] = {lane, 64 + lane};
   bool done[2] = {lane >= n2, 64 + lane >= n2};
   const int nb = n2 >> 4;
+  // pivot search of column j (values k0, k1 of the lane's two rows), by the
+  // wave that owns the column: multipliers and pivot to slot sb
+  auto pivot = [&](int j, T k0, T k1, int sb) {
+    const T kj[2] = {k0, k1};
+    T v[2];
+    int key[2];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      T a = fabs(kj[sl]);
+      if (!(a == a)) a = T(INFINITY);
+      v[sl] = done[sl] ? T(-1) : a;
+      key[sl] = done[sl] ? 0x7fffffff : mypos[sl];
+    }
+    const int bs = (v[1] > v[0] || (v[1] == v[0] && key[1] < key[0])) ? 1 : 0;
+    const T vb = bs ? v[1] : v[0];
+    const int kb = bs ? key[1] : key[0];
+    T vmax;
+    int bk;  // position of the pivot row (uniform)
+    wave_argmax(vb, kb, vmax, bk);
+    const unsigned long long sel = __ballot(kb == bk);  // positions of rows not pivoted are distinct
+    const int plane = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(sel));
+    const int pslot = __builtin_amdgcn_readlane(bs, plane);
+    const T pv = bcast(pslot ? kj[1] : kj[0], plane);
+    const bool nz = pv != T(0);
+    const T rp = T(1) / pv;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int row = 64 * sl + lane;
+      if (row < n2) s_l[sb][row] = nz ? ((lane == plane && sl == pslot) ? rp : kj[sl] * rp) : T(0);
+    }
+    if (lane == 0) {
+      s_pl[sb][0] = plane;
+      s_pl[sb][1] = pslot;
+      s_pl[sb][2] = nz;
+      spiv[j] = bk;
+      spv[j] = pv;
+      if (!nz) atomicMin(info, info_base | (unsigned long long)j);
+    }
+  };
   for (int jb = 0; jb < nb; ++jb) {
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
       const int j = 16 * jb + jj;
       const int sb = jj & 1;
-      if (w == jb) {
-        T v[2];
-        int key[2];
-#pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
-          T a = fabs(kc[sl][jj]);
-          if (!(a == a)) a = T(INFINITY);
-          v[sl] = done[sl] ? T(-1) : a;
-          key[sl] = done[sl] ? 0x7fffffff : mypos[sl];
-        }
-        const int bs = (v[1] > v[0] || (v[1] == v[0] && key[1] < key[0])) ? 1 : 0;
-        const T vb = bs ? v[1] : v[0];
-        const int kb = bs ? key[1] : key[0];
-        T vmax;
-        int bk;  // position of the pivot row (uniform)
-        wave_argmax(vb, kb, vmax, bk);
-        const unsigned long long sel = __ballot(kb == bk);  // positions of rows not pivoted are distinct
-        const int plane = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(sel));
-        const int pslot = __builtin_amdgcn_readlane(bs, plane);
-        const T pv = bcast(pslot ? kc[1][jj] : kc[0][jj], plane);
-        const bool nz = pv != T(0);
-        const T rp = T(1) / pv;
-#pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
-          const int row = 64 * sl + lane;
-          if (row < n2) s_l[sb][row] = nz ? ((lane == plane && sl == pslot) ? rp : kc[sl][jj] * rp) : T(0);
-        }
-        if (lane == 0) {
-          s_pl[sb][0] = plane;
-          s_pl[sb][1] = pslot;
-          s_pl[sb][2] = nz;
-          spiv[j] = bk;
-          spv[j] = pv;
-          if (!nz) atomicMin(info, info_base | (unsigned long long)j);
-        }
-      }
+      // the first column of a block; the others were searched ahead (below)
+      if (jj == 0 && w == jb) pivot(j, kc[0][0], kc[1][0], sb);
       __syncthreads();
       const int plane = __builtin_amdgcn_readfirstlane(s_pl[sb][0]);
       const int pslot = __builtin_amdgcn_readfirstlane(s_pl[sb][1]);
@@ -755,25 +772,28 @@ __device__ __forceinline__ void block_gj2(T* K, int n2, int lane, int w, int* sp
           mypos[sl] = j;
         }
       }
-      if (nz) {  // uniform; a zero pivot (reported) leaves the rows as they are
-        auto elim = [&](T (&x)[2]) {
-          const T p = bcast(pslot ? x[1] : x[0], plane);
+      auto elim_col = [&](T (&m)[2][16], int c) {
+        const T p = bcast(pslot ? m[1][c] : m[0][c], plane);
 #pragma unroll
-          for (int sl = 0; sl < 2; ++sl) x[sl] = me[sl] ? x[sl] * l[sl] : x[sl] - l[sl] * p;
-        };
-        auto elim_col = [&](T (&m)[2][16], int c) {
-          T x[2] = {m[0][c], m[1][c]};
-          elim(x);
-          m[0][c] = x[0];
-          m[1][c] = x[1];
-        };
-        if (w == jb) {
-#pragma unroll
-          for (int c = jj + 1; c < 16; ++c) elim_col(kc, c);
-        } else if (w > jb) {
-#pragma unroll
-          for (int c = 0; c < 16; ++c) elim_col(kc, c);
+        for (int sl = 0; sl < 2; ++sl) m[sl][c] = me[sl] ? m[sl][c] * l[sl] : m[sl][c] - l[sl] * p;
+      };
+      // the owner eliminates column j + 1 first and searches its pivot
+      // before the rest of its work (a zero pivot, reported, leaves the rows
+      // as they are)
+      if (w == jb) {
+        if (jj < 15) {
+          if (nz) elim_col(kc, jj + 1);
+          pivot(j + 1, kc[0][jj + 1], kc[1][jj + 1], sb ^ 1);
         }
+        if (nz) {
+#pragma unroll
+          for (int c = jj + 2; c < 16; ++c) elim_col(kc, c);
+        }
+      } else if (w > jb && nz) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) elim_col(kc, c);
+      }
+      if (nz) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) elim_col(ac, c);
       }
