@@ -169,7 +169,10 @@ def _kernel_table(kt, mods, steps, peak_flops):
             mdl = mods[name]
             avg_s = ms / cnt / 1e3
             fl, by = mdl["flops"] / mdl["launches"], mdl["bytes"] / mdl["launches"]
-            if mdl.get("bound") == "mfma":
+            # a kernel without a fixed bound is priced against whichever roof its
+            # intensity reaches first: HBM below the ridge point, MFMA above it
+            bound = mdl.get("bound") or ("mfma" if fl / by > peak_flops / PEAK["hbm"] else "hbm")
+            if bound == "mfma":
                 d.update(bound="mfma", achieved=fl / avg_s / 1e12, peak=peak_flops / 1e12, unit="TFLOP/s")
             else:
                 d.update(bound="hbm", achieved=by / avg_s / 1e9, peak=PEAK["hbm"] / 1e9, unit="GB/s")
