@@ -303,12 +303,100 @@ __device__ __forceinline__ void form_k(T* K, const T* Pa, const T* Pb, int r, in
   }
 }
 
+// Element e = tid + u * NT (u = 0, 1, ...) of an n2-row column-major block as
+// (row, column), stepped without a division per element.
+struct BlockWalk {
+  int k, c, dq, dr, n2;
+  __device__ __forceinline__ BlockWalk(int tid, int nt, int n2_) : n2(n2_) {
+    k = tid % n2;
+    c = tid / n2;
+    dq = nt / n2;
+    dr = nt % n2;
+  }
+  __device__ __forceinline__ void next() {
+    k += dr;
+    c += dq;
+    if (k >= n2) {
+      k -= n2;
+      ++c;
+    }
+  }
+};
+
+// form_k for the inverse route (n2 * n2 <= NT * NPT): every thread issues its
+// NPT loads in batches of NB, each entry read from the one product it comes
+// from
+template <typename T, int NT, int NPT, int NB>
+__device__ __forceinline__ void form_k_batched(T* K, const T* Pa, const T* Pb, int r, int Rp, int tid) {
+  static_assert(NPT % NB == 0, "whole batches");
+  const int n2 = 2 * r;
+  asm volatile("" : "+v"(tid));
+  BlockWalk it(tid, NT, n2);
+  for (int u0 = 0; u0 < NPT; u0 += NB) {
+    T v[NB];
+    BlockWalk st = it;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int i = it.k, j = it.c;
+      T x = (i < r ? j - r == i : i - r == j) ? T(1) : T(0);
+      if (j < n2) {
+        if (i < r && j < r) x = Pa[i + (int64_t)(Rp + j) * r];
+        else if (i >= r && j >= r) x = Pb[(i - r) + (int64_t)(Rp + j - r) * r];
+      }
+      v[u] = x;
+      it.next();
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      if (st.c < n2) K[st.k + st.c * n2] = v[u];
+      st.next();
+    }
+  }
+}
+
+// One 64-column chunk of the right-hand sides [W_a; W_b] (columns c0 ..
+// c0 + 63 of the children's products, zero past Rp): NPT values per thread
+// loaded in one batch (64 * n2 <= NT * NPT), then stored to LDS as
+// [column][row] with ld n2 + 1.
+template <typename T, int NT, int NPT>
+struct RhsChunk {
+  T v[NPT];
+  __device__ __forceinline__ void load(const T* Pa, const T* Pb, int r, int Rp, int c0, int tid) {
+    // an opaque copy of tid: the per-element addresses are not hoisted out of
+    // the caller's chunk loop (they would stay live in registers)
+    asm volatile("" : "+v"(tid));
+    BlockWalk it(tid, NT, 2 * r);
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      const int k = it.k, col = c0 + it.c;
+      T x = T(0);
+      if (it.c < 64 && col < Rp) x = k < r ? Pa[k + (int64_t)col * r] : Pb[(k - r) + (int64_t)col * r];
+      v[u] = x;
+      it.next();
+    }
+  }
+  __device__ __forceinline__ void store(T* Rs, int r, int tid) const {
+    const int n2 = 2 * r, ldr = n2 + 1;
+    BlockWalk it(tid, NT, n2);
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      if (it.c < 64) Rs[it.c * ldr + it.k] = v[u];
+      it.next();
+    }
+  }
+};
+
 // Gauss-Jordan elimination with partial pivoting on [K | I] for n2 <= 64,
 // n2 % 16 == 0, with the same register layout and pivot rule as block_lu
 // (lane i holds row i, wave w columns 16w .. 16w+15 of K and of the augmented
 // block).  Step j eliminates column j from every other row, including the
-// rows pivoted earlier, and scales the pivot row; afterwards the augmented
-// row of the row pivoted at step j is row j of K^{-1}, written to K (col-major).
+// rows pivoted earlier.  The pivot rows are divided by their pivots only at
+// the end (a row scaled later is the same multiple of the row scaled at once
+// through every later elimination, which is linear in it), so each step is
+// one multiply-add per entry; rows not yet pivoted are not affected, so the
+// pivots are those of scaling at once.  Afterwards the augmented row of the
+// row pivoted at step j, divided by its pivot, is row j of K^{-1}, written to
+// K (col-major).
 // spiv[j] records the position the row pivoted at step j came from (an
 // interchange with position j, as LAPACK's ipiv) and spv[j] its pivot value:
 // the pivots are those of LU with partial pivoting, so they give det K.
@@ -340,8 +428,8 @@ __device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, int* spi
     const T pv = bcast(kj, plane);
     const bool nz = pv != T(0);
     const T rp = T(1) / pv;
-    // multipliers of the other rows; the pivot row's own entry is the scale 1 / pivot
-    s_l[sb][lane] = (lane < n2 && nz) ? (lane == plane ? rp : kj * rp) : T(0);
+    // multipliers of the other rows; the pivot row keeps its values (scaled at the end)
+    s_l[sb][lane] = (lane < n2 && nz && lane != plane) ? kj * rp : T(0);
     if (lane == 0) {
       s_pl[sb][0] = plane;
       s_pl[sb][1] = nz;
@@ -370,7 +458,7 @@ __device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, int* spi
       }
       auto elim = [&](T& x) {
         const T p = bcast(x, plane);
-        x = me ? x * l : x - l * p;
+        x = x - l * p;  // l = 0 in the pivot row
       };
       // columns left of j are zero in the pivot row: nothing to do there.
       // The owner eliminates column j + 1 first and searches its pivot
@@ -396,10 +484,14 @@ __device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, int* spi
     }
   }
   __syncthreads();  // every wave has read K before it is overwritten
+  // the row pivoted at step mypos, divided by its pivot (left as it is after a
+  // zero pivot, which is reported)
+  const T pvm = lane < n2 ? spv[mypos] : T(1);
+  const T sc = pvm != T(0) ? T(1) / pvm : T(1);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     const int col = 16 * w + c;
-    if (lane < n2 && col < n2) K[mypos + col * n2] = ac[c];
+    if (lane < n2 && col < n2) K[mypos + col * n2] = ac[c] * sc;
   }
 }
 
@@ -631,7 +723,7 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_inv_kernel(int r, in
   const T* Pb = segs + (int64_t)seg_start[b] * elems;
   __shared__ int s_piv[64];
   __shared__ T s_pv[64];
-  form_k(K, Pa, Pb, r, Rp, tid);
+  form_k_batched<T, kCfThreads, 16, 8>(K, Pa, Pb, r, Rp, tid);
   __syncthreads();
   block_gj(K, n2, lane, wid, s_piv, s_pv, info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16));
   __syncthreads();
@@ -652,11 +744,10 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_inv_kernel(int r, in
   const int ldr = n2 + 1;
   T* Wg = W + (int64_t)g * n2 * Rp;
   for (int c0 = 0; c0 < Rp; c0 += 64) {
-    for (int e = tid; e < 64 * n2; e += kCfThreads) {
-      const int k = e % n2, c = e / n2;
-      const int col = min(c0 + c, Rp - 1);
-      const T v = k < r ? Pa[k + (int64_t)col * r] : Pb[(k - r) + (int64_t)col * r];
-      Rs[c * ldr + k] = (c0 + c < Rp) ? v : T(0);
+    {
+      RhsChunk<T, kCfThreads, 16> rhs;
+      rhs.load(Pa, Pb, r, Rp, c0, tid);
+      rhs.store(Rs, r, tid);
     }
     __syncthreads();
     if (act) {
@@ -688,7 +779,8 @@ __global__ __launch_bounds__(kCfThreads) void couple_factor_inv_kernel(int r, in
 // augmented block, lane i holding rows i (slot 0) and 64 + i (slot 1).  The
 // pivot of column j is the largest modulus among the rows not pivoted yet,
 // the lowest current position on ties (the rule of LU with partial
-// pivoting); spiv / spv and the final placement of the rows as block_gj.
+// pivoting); spiv / spv, the deferred scaling of the pivot rows and their
+// final placement as block_gj.
 template <typename T>
 __device__ __forceinline__ void block_gj2(T* K, int n2, int lane, int w, int* spiv, T* spv, unsigned long long* info,
                                           unsigned long long info_base) {
@@ -734,7 +826,7 @@ __device__ __forceinline__ void block_gj2(T* K, int n2, int lane, int w, int* sp
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       const int row = 64 * sl + lane;
-      if (row < n2) s_l[sb][row] = nz ? ((lane == plane && sl == pslot) ? rp : kj[sl] * rp) : T(0);
+      if (row < n2) s_l[sb][row] = (nz && !(lane == plane && sl == pslot)) ? kj[sl] * rp : T(0);
     }
     if (lane == 0) {
       s_pl[sb][0] = plane;
@@ -775,7 +867,7 @@ __device__ __forceinline__ void block_gj2(T* K, int n2, int lane, int w, int* sp
       auto elim_col = [&](T (&m)[2][16], int c) {
         const T p = bcast(pslot ? m[1][c] : m[0][c], plane);
 #pragma unroll
-        for (int sl = 0; sl < 2; ++sl) m[sl][c] = me[sl] ? m[sl][c] * l[sl] : m[sl][c] - l[sl] * p;
+        for (int sl = 0; sl < 2; ++sl) m[sl][c] = m[sl][c] - l[sl] * p;  // l = 0 in the pivot row
       };
       // the owner eliminates column j + 1 first and searches its pivot
       // before the rest of its work (a zero pivot, reported, leaves the rows
@@ -801,12 +893,16 @@ __device__ __forceinline__ void block_gj2(T* K, int n2, int lane, int w, int* sp
   }
   __syncthreads();  // every wave has read K before it is overwritten
 #pragma unroll
-  for (int sl = 0; sl < 2; ++sl)
+  for (int sl = 0; sl < 2; ++sl) {
+    const int row = 64 * sl + lane;
+    const T pvm = row < n2 ? spv[mypos[sl]] : T(1);
+    const T sc = pvm != T(0) ? T(1) / pvm : T(1);
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      const int row = 64 * sl + lane, col = 16 * w + c;
-      if (row < n2 && col < n2) K[mypos[sl] + col * n2] = ac[sl][c];
+      const int col = 16 * w + c;
+      if (row < n2 && col < n2) K[mypos[sl] + col * n2] = ac[sl][c] * sc;
     }
+  }
 }
 
 // Coupling factor for 64 < 2r <= 128 (2r % 16 == 0): K^{-1} by block_gj2 with
@@ -835,14 +931,7 @@ __global__ __launch_bounds__(kCf2Threads) void couple_factor_inv2_kernel(int r, 
   const T* Pb = segs + (int64_t)seg_start[b] * elems;
   __shared__ int s_piv[128];
   __shared__ T s_pv[128];
-  for (int e = tid; e < n2 * n2; e += kCf2Threads) {
-    const int i = e % n2, j = e / n2;
-    const bool da = i < r && j < r, db = i >= r && j >= r;
-    const T va = Pa[min(i, r - 1) + (int64_t)(Rp + min(j, r - 1)) * r];
-    const T vb = Pb[max(i - r, 0) + (int64_t)(Rp + max(j - r, 0)) * r];
-    const T id = (i < r ? j - r == i : i - r == j) ? T(1) : T(0);
-    K[i + j * n2] = da ? va : (db ? vb : id);
-  }
+  form_k_batched<T, kCf2Threads, 32, 8>(K, Pa, Pb, r, Rp, tid);
   __syncthreads();
   block_gj2(K, n2, lane, wid, s_piv, s_pv, info, ((unsigned long long)(L - level) << 44) | ((unsigned long long)g << 16));
   __syncthreads();
@@ -862,11 +951,10 @@ __global__ __launch_bounds__(kCf2Threads) void couple_factor_inv2_kernel(int r, 
   const int ldr = n2 + 1;
   T* Wg = W + (int64_t)g * n2 * Rp;
   for (int c0 = 0; c0 < Rp; c0 += 64) {
-    for (int e = tid; e < 64 * n2; e += kCf2Threads) {
-      const int k = e % n2, c = e / n2;
-      const int col = min(c0 + c, Rp - 1);
-      const T v = k < r ? Pa[k + (int64_t)col * r] : Pb[(k - r) + (int64_t)col * r];
-      Rs[c * ldr + k] = (c0 + c < Rp) ? v : T(0);
+    {
+      RhsChunk<T, kCf2Threads, 16> rhs;
+      rhs.load(Pa, Pb, r, Rp, c0, tid);
+      rhs.store(Rs, r, tid);
     }
     __syncthreads();
     if (act) {
