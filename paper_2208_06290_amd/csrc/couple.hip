@@ -404,7 +404,7 @@ template <typename T>
 __device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, int* spiv, T* spv, unsigned long long* info,
                                          unsigned long long info_base) {
   __shared__ T s_l[2][64];
-  __shared__ int s_pl[2][2];  // pivot lane, pivot value nonzero
+  __shared__ int s_pl[2][2];  // pivot lane, pivot position
   T kc[16], ac[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
@@ -432,7 +432,7 @@ __device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, int* spi
     s_l[sb][lane] = (lane < n2 && nz && lane != plane) ? kj * rp : T(0);
     if (lane == 0) {
       s_pl[sb][0] = plane;
-      s_pl[sb][1] = nz;
+      s_pl[sb][1] = bk;
       spiv[j] = bk;
       spv[j] = pv;
       if (!nz) atomicMin(info, info_base | (unsigned long long)j);
@@ -446,11 +446,12 @@ __device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, int* spi
       // the first column of a block; the others were searched ahead (below)
       if (jj == 0 && w == jb) pivot(j, kc[0], sb);
       __syncthreads();
+      // after a zero pivot (reported) every multiplier is zero and the rows
+      // stay as they are
       const int plane = __builtin_amdgcn_readfirstlane(s_pl[sb][0]);
-      const bool nz = s_pl[sb][1] != 0;
+      const int bk = __builtin_amdgcn_readfirstlane(s_pl[sb][1]);
       const T l = s_l[sb][lane];
       const bool me = lane == plane;
-      const int bk = __builtin_amdgcn_readfirstlane(__shfl(mypos, plane, 64));
       if (!done && !me && mypos == j) mypos = bk;  // the row displaced by the interchange
       if (me) {
         done = true;
@@ -462,25 +463,21 @@ __device__ __forceinline__ void block_gj(T* K, int n2, int lane, int w, int* spi
       };
       // columns left of j are zero in the pivot row: nothing to do there.
       // The owner eliminates column j + 1 first and searches its pivot
-      // before the rest of its work (a zero pivot, reported, leaves the rows
-      // as they are), so that search is off the other waves' critical path.
+      // before the rest of its work, so that search is off the other waves'
+      // critical path.
       if (w == jb) {
         if (jj < 15) {
-          if (nz) elim(kc[jj + 1]);
+          elim(kc[jj + 1]);
           pivot(j + 1, kc[jj + 1], sb ^ 1);
         }
-        if (nz) {
 #pragma unroll
-          for (int c = jj + 2; c < 16; ++c) elim(kc[c]);
-        }
-      } else if (w > jb && nz) {
+        for (int c = jj + 2; c < 16; ++c) elim(kc[c]);
+      } else if (w > jb) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) elim(kc[c]);
       }
-      if (nz) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) elim(ac[c]);
-      }
+      for (int c = 0; c < 16; ++c) elim(ac[c]);
     }
   }
   __syncthreads();  // every wave has read K before it is overwritten
@@ -785,7 +782,7 @@ template <typename T>
 __device__ __forceinline__ void block_gj2(T* K, int n2, int lane, int w, int* spiv, T* spv, unsigned long long* info,
                                           unsigned long long info_base) {
   __shared__ T s_l[2][128];
-  __shared__ int s_pl[2][3];  // pivot lane, pivot slot, pivot value nonzero
+  __shared__ int s_pl[2][3];  // pivot lane, pivot slot, pivot position
   T kc[2][16], ac[2][16];
 #pragma unroll
   for (int sl = 0; sl < 2; ++sl)
@@ -831,7 +828,7 @@ __device__ __forceinline__ void block_gj2(T* K, int n2, int lane, int w, int* sp
     if (lane == 0) {
       s_pl[sb][0] = plane;
       s_pl[sb][1] = pslot;
-      s_pl[sb][2] = nz;
+      s_pl[sb][2] = bk;
       spiv[j] = bk;
       spv[j] = pv;
       if (!nz) atomicMin(info, info_base | (unsigned long long)j);
@@ -845,9 +842,11 @@ __device__ __forceinline__ void block_gj2(T* K, int n2, int lane, int w, int* sp
       // the first column of a block; the others were searched ahead (below)
       if (jj == 0 && w == jb) pivot(j, kc[0][0], kc[1][0], sb);
       __syncthreads();
+      // after a zero pivot (reported) every multiplier is zero and the rows
+      // stay as they are
       const int plane = __builtin_amdgcn_readfirstlane(s_pl[sb][0]);
       const int pslot = __builtin_amdgcn_readfirstlane(s_pl[sb][1]);
-      const bool nz = s_pl[sb][2] != 0;
+      const int bk = __builtin_amdgcn_readfirstlane(s_pl[sb][2]);
       T l[2];
       bool me[2];
 #pragma unroll
@@ -855,7 +854,6 @@ __device__ __forceinline__ void block_gj2(T* K, int n2, int lane, int w, int* sp
         l[sl] = s_l[sb][min(64 * sl + lane, n2 - 1)];
         me[sl] = lane == plane && sl == pslot;
       }
-      const int bk = __builtin_amdgcn_readfirstlane(__shfl(pslot ? mypos[1] : mypos[0], plane, 64));
 #pragma unroll
       for (int sl = 0; sl < 2; ++sl) {
         if (!done[sl] && !me[sl] && mypos[sl] == j) mypos[sl] = bk;  // the row displaced by the interchange
@@ -870,25 +868,20 @@ __device__ __forceinline__ void block_gj2(T* K, int n2, int lane, int w, int* sp
         for (int sl = 0; sl < 2; ++sl) m[sl][c] = m[sl][c] - l[sl] * p;  // l = 0 in the pivot row
       };
       // the owner eliminates column j + 1 first and searches its pivot
-      // before the rest of its work (a zero pivot, reported, leaves the rows
-      // as they are)
+      // before the rest of its work
       if (w == jb) {
         if (jj < 15) {
-          if (nz) elim_col(kc, jj + 1);
+          elim_col(kc, jj + 1);
           pivot(j + 1, kc[0][jj + 1], kc[1][jj + 1], sb ^ 1);
         }
-        if (nz) {
 #pragma unroll
-          for (int c = jj + 2; c < 16; ++c) elim_col(kc, c);
-        }
-      } else if (w > jb && nz) {
+        for (int c = jj + 2; c < 16; ++c) elim_col(kc, c);
+      } else if (w > jb) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) elim_col(kc, c);
       }
-      if (nz) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) elim_col(ac, c);
-      }
+      for (int c = 0; c < 16; ++c) elim_col(ac, c);
     }
   }
   __syncthreads();  // every wave has read K before it is overwritten
