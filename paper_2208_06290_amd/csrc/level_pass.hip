@@ -220,9 +220,21 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
   if (NKS > 0) {
     const int nd = tl.node >> node_shift;
     const TZ* Wn = W + (int64_t)(nd >> 1) * w_pstride + (int64_t)(nd & 1) * ka;
-    for (int e = tid; e < kCw * ka; e += kLpThreads) {
-      const int c = e % kCw, k = e / kCw;
-      Ws[e] = (c < ncz) ? Wn[k + (int64_t)(c0 + c) * w_ld] : TZ(0);
+    if constexpr (BF) {
+      // W converted to bfloat16 once, as the update's A operands: element
+      // (k, c) to group k / 16, block c / 16, lane (k % 4, c % 16), slot
+      // (k / 4) % 4, so that one 8-byte read gives a lane its four values
+      __bf16* Wb = reinterpret_cast<__bf16*>(Ws);
+      for (int e = tid; e < kCw * ka; e += kLpThreads) {
+        const int c = e % kCw, k = e / kCw;
+        const TZ v = (c < ncz) ? Wn[k + (int64_t)(c0 + c) * w_ld] : TZ(0);
+        Wb[((((k >> 4) * NCB + (c >> 4)) * 4 + (k & 3)) * 16 + (c & 15)) * 4 + ((k >> 2) & 3)] = (__bf16)v;
+      }
+    } else {
+      for (int e = tid; e < kCw * ka; e += kLpThreads) {
+        const int c = e % kCw, k = e / kCw;
+        Ws[e] = (c < ncz) ? Wn[k + (int64_t)(c0 + c) * w_ld] : TZ(0);
+      }
     }
   }
 
@@ -332,19 +344,18 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
   // update of one 16-row MFMA block, and its contribution to the product
   auto update = [&](V (&acc)[NCB], const TZ (&acur)[NKS > 0 ? NKS : 1]) {
     if constexpr (BF) {
-      // groups of four K-steps as one bfloat16 MFMA (NKS is a multiple of 4)
+      // groups of four K-steps as one bfloat16 MFMA (NKS is a multiple of 4);
+      // the row's A values are packed once per group, W was packed when staged
+      const s4* Wp = reinterpret_cast<const s4*>(Ws);
 #pragma unroll
-      for (int g = 0; g < NKS / 4; ++g)
+      for (int g = 0; g < NKS / 4; ++g) {
+        TZ av4[4];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          TZ wv[4], av4[4];
+        for (int j = 0; j < 4; ++j) av4[j] = acur[4 * g + j];
+        const s4 ap = pack_bf16(av4);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            wv[j] = Ws[(4 * (4 * g + j) + lq) * kCw + 16 * cb + li];
-            av4[j] = acur[4 * g + j];
-          }
-          acc[cb] = Mma16<TZ, true>::mma(wv, av4, acc[cb]);
-        }
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = mma_bf16(Wp[((g * NCB + cb) * 4 + lq) * 16 + li], ap, acc[cb]);
+      }
     } else {
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks)
@@ -365,6 +376,17 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) bv[kk][mb] = bt[(4 * kk + lq) * kBtLd + 16 * mb + li];
+    // bfloat16: the B1 operands packed once for every Z block
+    s4 bp[BF && MB > 0 ? MB : 1];
+    if constexpr (BF) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        TZ b4v[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) b4v[kk] = bv[kk][mb];
+        bp[mb] = pack_bf16(b4v);
+      }
+    }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
@@ -373,13 +395,9 @@ __global__ __launch_bounds__(kLpThreads, (MB > 2 || NKS > 8) ? 2 : 3) void level
         TZ zv4[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) zv4[kk] = zt[(4 * kk + lq) * kZtLd + li];
+        const s4 zp = pack_bf16(zv4);
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          TZ b4[4];
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) b4[kk] = bv[kk][mb];
-          pacc[mb][cb] = Mma16<TZ, true>::mma(b4, zv4, pacc[mb][cb]);
-        }
+        for (int mb = 0; mb < MB; ++mb) pacc[mb][cb] = mma_bf16(bp[mb], zp, pacc[mb][cb]);
       } else {
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {

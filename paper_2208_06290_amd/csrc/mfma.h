@@ -73,6 +73,18 @@ struct Mma16<float, true> {
   }
 };
 
+// bfloat16 operands packed once (round to nearest even, as the conversions
+// in Mma16<float, true>) and the 16 x 16 x 16 product on packed operands.
+__device__ __forceinline__ s4 pack_bf16(const float (&x)[4]) {
+  b4 v;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = (__bf16)x[j];
+  return __builtin_bit_cast(s4, v);
+}
+__device__ __forceinline__ f4 mma_bf16(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
 // Raw buffer access: a lane-uniform base in a buffer resource (scalar
 // registers), a 32-bit per-lane offset and a 32-bit lane-uniform offset.
 // Offsets are in bytes; callers keep every offset below 2^31.
