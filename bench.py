@@ -39,8 +39,8 @@ PEAK = dict(hbm=8.0e12, f64=78.6e12, f32=157.3e12, bf16=2.5e15)
 # and profiles/counters_n1m_synthetic_fp64_fp32_bf16.md).
 # It is reported only while the kernel source is the one it was measured on.
 LEVEL_PASS_TRAFFIC = dict(
-    source_sha256="f1ffc6731f9f193410057fa59cebcd4dd7af40eb6a521c3fcf9fe051f19d1355",
-    n=1 << 20, leaf=256, rank=32, bytes_per_launch=4.264e9)
+    source_sha256="000a3cfbe028865a382020c1e736d879689e56ac5eadf5b6fe90b1f86aea5e5b",
+    n=1 << 20, leaf=256, rank=32, bytes_per_launch=4.2646e9)
 
 # HBM traffic of one cross-approximation step (row + column launch) of the
 # construction of the double-layer matrix at N = 2^20, leaf 256, rank 32, from
