@@ -328,6 +328,28 @@ def test_singular_coupling_matrix_is_reported():
     assert e.value.status == 1 and e.value.info["level"] == 0
 
 
+@pytest.mark.parametrize("rank,leaf", [(16, 64), (64, 128)])
+def test_coupling_matrices_with_zero_generators(rank, leaf):
+    """V generators of level 2 set to zero: the two coupling matrices of
+    level 1 are [[0, I], [I, 0]] (eq. "e:k" with V_a^T Y_a = 0), so every
+    elimination step takes its pivot from the other half of the rows.  2r = 32
+    runs the four-wave Gauss-Jordan inverse, 2r = 128 the eight-wave one.
+    Solve, adjoint solve and log|det A| against the oracle and LAPACK."""
+    _say(f"zero generators rank {rank}")
+    n = 4096
+    inp = W.synthetic(n, leaf, rank, seed=21)
+    inp.V[rank:2 * rank, :] = 0.0   # columns [R_1, R_2) of V_big: level 2
+    H = O.from_inputs(inp)
+    A = H_().HODLRMatrix.from_inputs(inp.to(DEV))
+    F = H_().factor(A, "fp64")
+    B = _rhs(n, 2, 22)
+    assert _rel(_from_dev(F.solve(_to_dev(B))), O.solve(O.factor(H), B)) < 1e-12
+    assert _rel(_from_dev(F.solve_adjoint(_to_dev(B))), O.solve_adjoint(H, B)) < 1e-12
+    sign, la = F.slogdet()
+    s_o, l_o = np.linalg.slogdet(O.assemble_dense(H))
+    assert sign == s_o and abs(la - l_o) <= 1e-12 * max(1.0, abs(l_o))
+
+
 def test_bitwise_determinism():
     _say("determinism")
     inp, H, A = _build("leaf256_L3", seed=10)
